@@ -1,0 +1,52 @@
+"""CPU float64 oracle of semi-Lagrangian Metamorphosis / LDDMM shooting.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path. It shares no code
+with the HIP library.
+
+Parity status of each function (what pins it; tests/test_oracle_*.py):
+
+* gaussian_taps, conv_axis, smooth: SciPy ``correlate1d(mode='constant')``,
+  constant preservation away from edges, self-adjointness.
+* diff, diff_T: exactness on affine fields, dot-product transpose test,
+  closed-form boundary rows.
+* feet, interp, interp_grad, interp_T: SciPy ``map_coordinates(order=1,
+  mode='nearest')``, torch ``grid_sample(border, align_corners=True)``,
+  exact integer shifts, affine reproduction, dot-product transpose test,
+  central finite differences of interp.
+* step_given_v, step, shoot: identity at zero momentum, constant-image
+  invariants, maximum principle at rho = 0, exact integer shift, the sign of
+  the transport for a ramp, the constant-image closed form at T = 1.
+* cost_terms, cost_and_grad, step_adjoint: closed form at T = 1, central
+  finite differences on 16x16 (and 3-D) inputs, autograd of an independent
+  torch float64 program.
+* energy: diagnostic only, parity unpinned (the paper gives no numbers).
+* gradient_descent: parity unpinned (driver; its steps are pinned above).
+"""
+from .shooting import (  # noqa: F401
+    Feet,
+    Trajectory,
+    conv_axis,
+    cost,
+    cost_and_grad,
+    cost_terms,
+    diff,
+    diff_T,
+    divergence,
+    energy,
+    feet,
+    gaussian_taps,
+    gradient_descent,
+    grid_coords,
+    interp,
+    interp_T,
+    interp_grad,
+    max_displacement,
+    momentum_field,
+    shoot,
+    smooth,
+    step,
+    step_adjoint,
+    step_given_v,
+    velocity,
+)
