@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput of batched cost + dH/dp0 evaluations (forward shooting, cost,
+hand-written discrete adjoint with sqrt(T) checkpointing) on one MI355X.
+
+A step is one cost + gradient evaluation of every pair of the workload,
+replayed from the plan's captured HIP graph, with all inputs resident in HBM.
+The JSON line reports:
+
+* value: voxel-steps/s = sum_i N_i * T per evaluation / seconds (a step of the
+  scheme counts once per evaluation, although forward, recompute and adjoint
+  all visit it); pair_evals_per_s alongside;
+* unfused: the same evaluations through the per-pair, one-kernel-per-primitive
+  path of the same library, and the speed-up over it;
+* roofline: the kernel family with the largest share of the step time, its
+  algorithmic bytes per launch over its average launch duration (HIP events
+  around its launches on the stream they run on), against 8 TB/s;
+* cpu_baseline: the float64 oracle on the host, on a bounded sample of pairs.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "cost+grad evals/sec & voxel-steps/s, batched adjoint vs per-pair unfused, %HBM"
+HBM_PEAK_GBPS = 8000.0
+
+WORKLOADS = {
+    "c3": "64 ragged 2-D brain-slice pairs, H, W iid in {96,128,192,240,320}, sigma_i ~ U[2,6], "
+          "rho_i ~ U[0.05,1], T=20, cost+grad",
+    "c2": "one 2-D 240x240 brain-slice pair, sigma=5, rho=0.5, T=20, cost+grad",
+    "c4": "one 3-D 160x192x160 brain-volume pair, sigma=4, rho=0.3, T=15, cost+grad",
+    "c5": "16 ragged 3-D brain volumes from {96^3, 128^3, 128x160x128, 160x192x160}, sigma=4, "
+          "rho_i ~ U[0.1,1], T=15, cost+grad",
+}
+
+# Algorithmic (compulsory) bytes per voxel of one launch of each kernel family:
+# float32 fields each kernel must read and write once, d = 2 or 3.
+def bytes_per_voxel(name: str, d: int) -> int:
+    f = 4
+    table = {
+        "xpass_gradmul": 2 + d,          # read I, z; write d channels
+        "xpass_plain": 2 * d,            # read d, write d
+        "spass_mid": 2 * d,
+        "spass_v": 2 * d,
+        "spass_mbar": 2 * d,
+        "advect": d + 2 + 2,             # read v, I, z; write I', z'
+        "advect_adjoint": (d + 2 + 2) + (2 + 1 + d),  # read v, I, z, Ibar', zbar'; write scatter, divbar, vbar
+        "divT": (1 + d) + d,
+        "epilogue": (d + 2 + 2) + (2 + 2),  # read mbar, I, z, scatter; write Ibar, zbar, clear scatter
+        "init": 4,
+        "fill": 0,
+        "finalize": 0,
+    }
+    return f * table.get(name, 0)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device_common.h", "shoot_internal.h"):
+        with open(os.path.join(ROOT, "paper_2106_08817_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, launches_ref: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(workload, {}).get(kernel)
+    if not entry or entry.get("source_sha") != kernel_source_sha():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def build_plan(workload, flags, torch, api):
+    specs = []
+    for p in workload.pairs:
+        t = lambda a: torch.from_numpy(a).to("cuda:0")  # noqa: E731
+        specs.append(api.PairSpec(t(p.source), t(p.p0), p.rho, p.sigma, p.lam, t(p.target)))
+    return api.Plan(specs, workload.T, flags, outputs=("grad", "cost"))
+
+
+def time_evals(plan, n, torch):
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(n):
+        plan.grad()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1000.0
+
+
+def cpu_baseline(workload, seconds):
+    """The oracle as it stands, single-threaded NumPy, on the first pairs of the
+    workload until about `seconds` of work (at least one pair)."""
+    import oracle
+
+    vs, used, done = 0, 0.0, 0
+    for p in workload.pairs:
+        t0 = time.perf_counter()
+        oracle.cost_and_grad(p.source, p.target, p.p0, p.rho, p.sigma, p.lam, workload.T)
+        used += time.perf_counter() - t0
+        vs += p.size * workload.T
+        done += 1
+        if used >= seconds:
+            break
+    return {"value": vs / used, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {len(workload.pairs)} pairs, one float64 cost+grad evaluation each "
+                      f"({used:.1f} s, single-threaded NumPy)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=5, help="evaluations timed per kernel")
+    ap.add_argument("--unfused-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-unfused", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--flags", type=int, default=0, help="extra plan flags (bit mask of SHOOT_*)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): the pairs of a "
+              "batch are independent, and this build measures one GPU's share.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synthetic
+    from paper_2106_08817_amd import api
+
+    t_gen = time.perf_counter()
+    wl = synthetic.workload(args.workload, p0_kind="realistic")
+    d = wl.pairs[0].ndim
+    voxels = sum(p.size for p in wl.pairs)
+    vsteps = voxels * wl.T
+    print(f"[bench] {args.workload}: {len(wl.pairs)} pairs, {voxels} voxels, T={wl.T} "
+          f"(inputs {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+
+    plan = build_plan(wl, args.flags, torch, api)
+    for _ in range(args.warmup):
+        plan.grad()
+    torch.cuda.synchronize()
+    secs = time_evals(plan, args.steps, torch)
+    ms_per_step = 1000.0 * secs / args.steps
+    value = vsteps * args.steps / secs
+    costs = plan.out_cost[:, 0].cpu().numpy()
+    assert np.all(np.isfinite(costs)), "non-finite cost"
+    print(f"[bench] fused: {ms_per_step:.3f} ms/eval, {value:.4g} voxel-steps/s", file=sys.stderr, flush=True)
+
+    # per-kernel durations: HIP events around every launch on the launch stream
+    plan.set_profiling(True)
+    plan.reset_stats()
+    for _ in range(args.profile_steps):
+        plan.grad()
+    stats = plan.kernel_stats()
+    plan.set_profiling(False)
+    kernels = {}
+    for name, (n, ms) in stats.items():
+        if n == 0:
+            continue
+        per_eval = n / args.profile_steps
+        bpl = bytes_per_voxel(name, d) * voxels
+        avg = ms / n
+        kernels[name] = {"launches_per_eval": per_eval, "avg_us": 1000.0 * avg,
+                         "ms_per_eval": ms / args.profile_steps,
+                         "algorithmic_GBps": (bpl / (avg / 1000.0)) / 1e9 if avg > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_eval"])
+    dk = kernels[dom]
+    bpl = bytes_per_voxel(dom, d) * voxels
+    achieved = bpl / (dk["avg_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(dom, args.workload, None)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": bpl, "avg_launch_us": dk["avg_us"]}
+    step_bytes = sum(bytes_per_voxel(k, d) * voxels * v["launches_per_eval"] for k, v in kernels.items())
+    print(f"[bench] dominant kernel {dom}: {dk['avg_us']:.1f} us/launch, {achieved:.0f} GB/s algorithmic",
+          file=sys.stderr, flush=True)
+
+    unfused = None
+    if not args.no_unfused:
+        uplan = build_plan(wl, api.SHOOT_UNFUSED, torch, api)
+        uplan.grad()
+        torch.cuda.synchronize()
+        usecs = time_evals(uplan, args.unfused_steps, torch)
+        uval = vsteps * args.unfused_steps / usecs
+        unfused = {"value": uval, "unit": "voxel-steps/s", "ms_per_eval": 1000.0 * usecs / args.unfused_steps,
+                   "speedup": value / uval,
+                   "path": "same library, per pair in sequence, one kernel per primitive, full trajectory "
+                           "stored, global-atomic scatter, no graph"}
+        du = np.abs(np.array([float(uplan.out_cost[i, 0]) for i in range(len(wl.pairs))]) - costs)
+        unfused["max_rel_cost_diff"] = float(np.max(du / np.abs(costs)))
+        uplan.close()
+        print(f"[bench] unfused: {unfused['ms_per_eval']:.1f} ms/eval, speed-up {unfused['speedup']:.1f}x",
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "pairs": len(wl.pairs),
+                   "voxels": voxels, "T": wl.T, "p0": "realistic (smooth, ~0.3 px per step)",
+                   "flags": args.flags, "mode": "batched tile lists, sqrt(T) checkpoints, captured HIP graph"},
+        "pair_evals_per_s": len(wl.pairs) * args.steps / secs,
+        "step_algorithmic_GBps": step_bytes / (ms_per_step / 1000.0) / 1e9,
+        "step_hbm_frac": step_bytes / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBPS,
+        "roofline": roofline,
+        "unfused": unfused,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "kernel_source_sha": kernel_source_sha(),
+    }
+    print(json.dumps(out))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * shoot.h - C ABI of the MI355X (gfx950) library for semi-Lagrangian geodesic
+ * shooting in Metamorphosis / LDDMM image registration
+ * (François, Gori, Glaunès, "Metamorphic image registration using a
+ * semi-Lagrangian scheme", arXiv:2106.08817).
+ *
+ * What the library computes, for each image pair (S, J) and initial momentum
+ * p0 (Methods, Eqs. 1-9 and the semi-Lagrangian section), with T steps of
+ * dt = 1/T on a unit-spaced grid, from (I_0, z_0) = (S, p0):
+ *
+ *   m_a  = z_t * D_a I_t                      (D_a: clamped central difference)
+ *   v_a  = -G m_a                             (Eq. 3; G: separable Gaussian,
+ *                                              taps exp(-k^2/2 sigma^2) normalised
+ *                                              to sum 1, |k| <= floor(3 sigma),
+ *                                              zero padding)
+ *   y    = q - dt v(q)                        (foot points, semi-Lagrangian step)
+ *   Ih   = Interp(I_t; y), zh = Interp(z_t; y) (clamped bilinear / trilinear)
+ *   I_{t+1} = Ih + rho dt zh                  (image characteristic, Eqs. 5-6)
+ *   z_{t+1} = zh (1 - dt sum_a D_a v_a)       (momentum characteristic, Eqs. 7-9)
+ *
+ * and the inexact-matching cost (Eq. 4), with norms taken as plain sums:
+ *
+ *   H = 1/2 ||I_T - J||^2 + lambda ( <m_0, G m_0> + rho ||p0||^2 ).
+ *
+ * The paper's mu is taken equal to rho (the LDDMM limit is rho = mu -> 0), so
+ * rho = 0 is pure LDDMM. shoot_grad_p0 returns dH/dp0, the exact derivative
+ * of this discrete H (a hand-written discrete adjoint of the whole loop; on a
+ * grid line the interpolation derivative is one-sided, cell floor(c), and it
+ * is zero where a foot coordinate is clamped at or beyond a border).
+ *
+ * Arithmetic is float32 throughout.
+ *
+ * Memory and streams
+ *   Every buffer the kernels touch is owned by the caller: inputs, outputs and
+ *   one workspace. The library allocates no device memory. A plan owns host
+ *   memory, a capture stream and (unless SHOOT_NO_GRAPH) captured HIP graphs.
+ *   Device pointers must stay valid and unchanged from shoot_plan_bind to
+ *   shoot_plan_destroy (graphs replay them). Streams are hipStream_t passed as
+ *   void*; NULL means the null stream. Execution calls are asynchronous on the
+ *   stream and never synchronise it.
+ *
+ * Errors
+ *   Every entry point returns a shoot_status. Arguments are validated on the
+ *   host before anything is enqueued; a failed call enqueues nothing.
+ *   shoot_last_error() returns a thread-local message describing the last
+ *   failure of the calling thread. NaN / Inf in the inputs propagate.
+ */
+#ifndef SHOOT_H
+#define SHOOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum shoot_status {
+  SHOOT_OK = 0,
+  SHOOT_E_ARG = -1,       /* bad argument: null pointer, T < 1, sigma <= 0, ... */
+  SHOOT_E_SHAPE = -2,     /* ndim not in {2,3}, an extent < 2, mixed ndim, too large */
+  SHOOT_E_WORKSPACE = -3, /* workspace missing, misaligned or too small */
+  SHOOT_E_BUDGET = -4,    /* one pair alone exceeds the memory budget */
+  SHOOT_E_HIP = -5,       /* a HIP runtime call failed (message has the HIP error) */
+  SHOOT_E_STATE = -6      /* call out of order (e.g. execute before bind) */
+} shoot_status;
+
+/*
+ * One image pair. Layout: C-contiguous float32, last axis contiguous ("x");
+ * shape = (n0, n1) in 2-D or (n0, n1, n2) in 3-D, each extent >= 2.
+ * All pointers are device pointers, at least 4-byte aligned (16-byte
+ * recommended). image (S) and p0 are required. target (J) is required by
+ * shoot_cost and shoot_grad_p0 and optional for shoot_forward. Any out_*
+ * pointer may be NULL when that output is not wanted, except out_grad for
+ * shoot_grad_p0.
+ *   out_image    [N]  I_T              (shoot_forward)
+ *   out_momentum [N]  z_T              (shoot_forward)
+ *   out_grad     [N]  dH/dp0           (shoot_grad_p0)
+ *   out_cost     [3]  (H, 1/2||I_T-J||^2, lambda(<m0,Gm0> + rho||p0||^2))
+ *                     (shoot_cost, shoot_grad_p0, and shoot_forward when
+ *                     target is given)
+ * rho >= 0 weighs the intensity residual; sigma > 0 is the kernel width in
+ * pixels (sigma < 32/3, i.e. radius floor(3 sigma) <= 31); lambda >= 0 weighs
+ * the regulariser.
+ */
+typedef struct shoot_pair {
+  int32_t ndim;
+  int32_t shape[3];
+  float rho;
+  float sigma;
+  float lambda;
+  const float* image;
+  const float* target;
+  const float* p0;
+  float* out_image;
+  float* out_momentum;
+  float* out_grad;
+  float* out_cost;
+} shoot_pair;
+
+typedef struct shoot_plan_s* shoot_plan;
+
+/* Plan flags. */
+#define SHOOT_FULL_STORE 1u            /* keep all T states instead of sqrt(T) checkpoints */
+#define SHOOT_UNFUSED 2u               /* per-pair, one kernel per primitive (baseline) */
+#define SHOOT_NO_GRAPH 4u              /* launch kernels eagerly, no internal HIP graph */
+#define SHOOT_FORCE_GLOBAL_SCATTER 8u  /* adjoint scatter through global atomics only */
+
+/* Library version string. Never NULL. */
+const char* shoot_version(void);
+
+/* Thread-local message of the calling thread's last failure ("" if none). */
+const char* shoot_last_error(void);
+
+/*
+ * Create a plan for n_pairs >= 1 pairs sharing the step count T >= 1
+ * (dt = 1/T). All pairs must have the same ndim. The descriptors are copied;
+ * their device pointers are used from shoot_plan_bind on. Host-only: no HIP
+ * call is made. budget_bytes caps the workspace (0 = no cap): pairs are
+ * grouped into waves that each fit, run one after another in the same
+ * workspace; SHOOT_E_BUDGET if a single pair does not fit.
+ * On success *out receives the plan; on failure *out is set to NULL.
+ */
+shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t T,
+                               uint32_t flags, size_t budget_bytes, shoot_plan* out);
+
+/* Workspace size in bytes (host-only). The workspace must be 256-byte aligned. */
+shoot_status shoot_plan_workspace_bytes(shoot_plan plan, size_t* bytes);
+
+/* Number of admission waves the plan runs (1 unless a budget forced more). */
+shoot_status shoot_plan_waves(shoot_plan plan, int32_t* waves);
+
+/*
+ * Attach the caller-owned device workspace and upload the plan's descriptors
+ * and tile lists into it, asynchronously on `stream`. May be called again to
+ * rebind (captured graphs are then discarded).
+ */
+shoot_status shoot_plan_bind(shoot_plan plan, void* workspace, size_t bytes, void* stream);
+
+/*
+ * Pick the fastest launch shapes for this plan on the current device by
+ * timing the candidate kernels with HIP events on `stream` (synchronising).
+ * Results do not depend on the choice (bit-identical outputs). Optional.
+ */
+shoot_status shoot_autotune(shoot_plan plan, void* stream);
+
+/*
+ * Shoot every pair: writes out_image (I_T) and out_momentum (z_T) when not
+ * NULL, and out_cost when both target and out_cost are given.
+ */
+shoot_status shoot_forward(shoot_plan plan, void* stream);
+
+/* Shoot every pair and write its cost (H, data, reg) to out_cost. */
+shoot_status shoot_cost(shoot_plan plan, void* stream);
+
+/*
+ * Shoot every pair, then run the discrete adjoint backwards through the loop
+ * (states restored from sqrt(T) checkpoints by recomputation, unless
+ * SHOOT_FULL_STORE) and write dH/dp0 to out_grad, and the cost to out_cost
+ * when given.
+ */
+shoot_status shoot_grad_p0(shoot_plan plan, void* stream);
+
+/*
+ * Diagnostics. With profiling enabled, execution calls run eagerly (no graph)
+ * with a HIP event pair around every kernel launch on the launch stream, and
+ * synchronise the stream before returning; per-kernel launch counts and total
+ * milliseconds accumulate until reset. shoot_plan_kernel_stats returns
+ * SHOOT_E_ARG for an index past the last kernel; *name stays owned by the
+ * library.
+ */
+shoot_status shoot_plan_set_profiling(shoot_plan plan, int32_t enable);
+shoot_status shoot_plan_reset_stats(shoot_plan plan);
+shoot_status shoot_plan_kernel_stats(shoot_plan plan, int32_t index, const char** name, int64_t* launches,
+                                     double* total_ms);
+
+/* Release the plan's host memory, capture stream and graphs. NULL is a no-op. */
+shoot_status shoot_plan_destroy(shoot_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHOOT_H */

@@ -1,0 +1,254 @@
+"""Torch-facing wrappers of the HIP library. PyTorch supplies device memory and
+the stream; every step of the shooting and of its adjoint runs in the
+library's kernels.
+
+* :class:`Plan`        - a bound plan over a list of pairs (CUDA float32 tensors)
+* :class:`ShootCost`   - ``torch.autograd.Function`` whose forward evaluates the
+                         cost and dH/dp0 with the hand-written adjoint and whose
+                         backward returns ``g * dH/dp0``
+* :func:`shoot_cost`   - functional form of :class:`ShootCost`
+* :func:`gradient_descent` - batched fixed-step descent on p0
+"""
+from __future__ import annotations
+
+import ctypes
+from collections import OrderedDict
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import (SHOOT_FORCE_GLOBAL_SCATTER, SHOOT_FULL_STORE, SHOOT_NO_GRAPH,  # noqa: F401
+                   SHOOT_UNFUSED, ShootError)
+
+__all__ = ["PairSpec", "Plan", "ShootCost", "shoot_cost", "gradient_descent",
+           "SHOOT_FULL_STORE", "SHOOT_UNFUSED", "SHOOT_NO_GRAPH", "SHOOT_FORCE_GLOBAL_SCATTER"]
+
+
+@dataclass
+class PairSpec:
+    """One pair: source ``image``, ``target`` (optional for forward only),
+    initial momentum ``p0``, and the scalars rho, sigma, lam."""
+
+    image: torch.Tensor
+    p0: torch.Tensor
+    rho: float
+    sigma: float
+    lam: float = 0.01
+    target: Optional[torch.Tensor] = None
+
+
+def _check_field(t: torch.Tensor, name: str, device: torch.device, shape=None) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != device or t.device.type != "cuda":
+        raise ValueError(f"{name} must live on {device} (a GPU device)")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A plan for a batch of pairs sharing T, bound to a workspace.
+
+    Output tensors are allocated here and stay fixed (captured graphs replay
+    their addresses): ``out_image``, ``out_momentum``, ``out_grad`` (lists,
+    one tensor per pair) and ``out_cost`` (tensor [n_pairs, 3] =
+    (H, data, reg)). Input tensors must stay alive and in place; their
+    contents may change between calls (e.g. p0 updated in place).
+    """
+
+    def __init__(self, pairs: Sequence[PairSpec], T: int, flags: int = 0, budget_bytes: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None, outputs: Sequence[str] = ("image", "momentum",
+                                                                                       "grad", "cost")):
+        self._lib = _lib.load()
+        self._plan = None
+        if len(pairs) == 0:
+            raise ValueError("at least one pair is needed")
+        device = pairs[0].image.device
+        self.device = device
+        self.T = int(T)
+        self.flags = int(flags)
+        self.pairs = list(pairs)
+        n = len(self.pairs)
+        outs = set(outputs)
+        with torch.cuda.device(device):
+            self.out_cost = torch.zeros((n, 3), dtype=torch.float32, device=device) if "cost" in outs else None
+            self.out_image, self.out_momentum, self.out_grad = [], [], []
+            arr = (_lib.ShootPair * n)()
+            for i, ps in enumerate(self.pairs):
+                shp = tuple(ps.image.shape)
+                if len(shp) not in (2, 3):
+                    raise ValueError(f"pair {i}: image must be 2-D or 3-D")
+                _check_field(ps.image, f"pair {i} image", device)
+                _check_field(ps.p0, f"pair {i} p0", device, shp)
+                if ps.target is not None:
+                    _check_field(ps.target, f"pair {i} target", device, shp)
+                oi = torch.empty_like(ps.image) if "image" in outs else None
+                om = torch.empty_like(ps.image) if "momentum" in outs else None
+                og = torch.empty_like(ps.image) if "grad" in outs else None
+                self.out_image.append(oi)
+                self.out_momentum.append(om)
+                self.out_grad.append(og)
+                d = arr[i]
+                d.ndim = len(shp)
+                for a in range(3):
+                    d.shape[a] = shp[a] if a < len(shp) else 0
+                d.rho = float(ps.rho)
+                d.sigma = float(ps.sigma)
+                d.lambda_ = float(ps.lam)
+                d.image = ps.image.data_ptr()
+                d.target = ps.target.data_ptr() if ps.target is not None else None
+                d.p0 = ps.p0.data_ptr()
+                d.out_image = oi.data_ptr() if oi is not None else None
+                d.out_momentum = om.data_ptr() if om is not None else None
+                d.out_grad = og.data_ptr() if og is not None else None
+                d.out_cost = (self.out_cost.data_ptr() + 12 * i) if self.out_cost is not None else None
+            self._desc = arr
+            handle = ctypes.c_void_p()
+            _lib.check(self._lib.shoot_plan_create(ctypes.cast(arr, ctypes.c_void_p), n, self.T, self.flags,
+                                                   int(budget_bytes), ctypes.byref(handle)), "shoot_plan_create")
+            self._plan = handle
+            nbytes = ctypes.c_size_t()
+            _lib.check(self._lib.shoot_plan_workspace_bytes(self._plan, ctypes.byref(nbytes)),
+                       "shoot_plan_workspace_bytes")
+            self.workspace_bytes = int(nbytes.value)
+            raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+            shift = (-raw.data_ptr()) % 256
+            self._raw = raw
+            self.workspace = raw[shift:shift + self.workspace_bytes]
+            _lib.check(self._lib.shoot_plan_bind(self._plan, self.workspace.data_ptr(), self.workspace_bytes,
+                                                 _stream_ptr(stream)), "shoot_plan_bind")
+
+    @property
+    def waves(self) -> int:
+        w = ctypes.c_int32()
+        _lib.check(self._lib.shoot_plan_waves(self._plan, ctypes.byref(w)), "shoot_plan_waves")
+        return int(w.value)
+
+    def _call(self, fn, name, stream):
+        if self._plan is None:
+            raise RuntimeError("plan is closed")
+        with torch.cuda.device(self.device):
+            _lib.check(fn(self._plan, _stream_ptr(stream)), name)
+
+    def forward(self, stream=None) -> None:
+        """I_T, z_T (and the cost where a target is given)."""
+        self._call(self._lib.shoot_forward, "shoot_forward", stream)
+
+    def cost(self, stream=None) -> None:
+        self._call(self._lib.shoot_cost, "shoot_cost", stream)
+
+    def grad(self, stream=None) -> None:
+        """Cost and dH/dp0 of every pair (hand-written discrete adjoint)."""
+        self._call(self._lib.shoot_grad_p0, "shoot_grad_p0", stream)
+
+    def autotune(self, stream=None) -> None:
+        self._call(self._lib.shoot_autotune, "shoot_autotune", stream)
+
+    def set_profiling(self, enable: bool) -> None:
+        """Eager launches with a HIP event pair around each kernel (diagnostics)."""
+        _lib.check(self._lib.shoot_plan_set_profiling(self._plan, 1 if enable else 0), "shoot_plan_set_profiling")
+
+    def reset_stats(self) -> None:
+        _lib.check(self._lib.shoot_plan_reset_stats(self._plan), "shoot_plan_reset_stats")
+
+    def kernel_stats(self) -> dict:
+        """{kernel family: (launches, total milliseconds)} since the last reset."""
+        out = {}
+        i = 0
+        while True:
+            name = ctypes.c_char_p()
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            st = self._lib.shoot_plan_kernel_stats(self._plan, i, ctypes.byref(name), ctypes.byref(n),
+                                                   ctypes.byref(ms))
+            if st != _lib.SHOOT_OK:
+                break
+            out[name.value.decode()] = (int(n.value), float(ms.value))
+            i += 1
+        return out
+
+    def close(self) -> None:
+        if self._plan is not None:
+            self._lib.shoot_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- autograd
+
+_PLAN_CACHE: "OrderedDict[tuple, Plan]" = OrderedDict()
+_PLAN_CACHE_SIZE = 8
+
+
+def _cached_plan(S, J, p0, rho, sigma, lam, T, flags):
+    key = (S.data_ptr(), J.data_ptr(), p0.data_ptr(), tuple(S.shape), float(rho), float(sigma), float(lam),
+           int(T), int(flags), S.device.index)
+    plan = _PLAN_CACHE.get(key)
+    if plan is None:
+        plan = Plan([PairSpec(S, p0, rho, sigma, lam, J)], T, flags, outputs=("grad", "cost"))
+        plan._keep = (S, J, p0)
+        _PLAN_CACHE[key] = plan
+        while len(_PLAN_CACHE) > _PLAN_CACHE_SIZE:
+            _PLAN_CACHE.popitem(last=False)[1].close()
+    else:
+        _PLAN_CACHE.move_to_end(key)
+    return plan
+
+
+class ShootCost(torch.autograd.Function):
+    """H(p0) for one pair; the gradient comes from the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, S, J, p0, rho, sigma, lam, T, flags=0):
+        plan = _cached_plan(S.detach(), J.detach(), p0.detach(), rho, sigma, lam, T, flags)
+        plan.grad()
+        ctx.save_for_backward(plan.out_grad[0].clone())
+        return plan.out_cost[0, 0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return None, None, g * grad, None, None, None, None, None
+
+
+def shoot_cost(S, J, p0, rho, sigma, lam=0.01, T=10, flags=0):
+    """Differentiable (w.r.t. p0) cost H of Eq. 4 for one pair."""
+    return ShootCost.apply(S, J, p0, rho, sigma, lam, T, flags)
+
+
+def gradient_descent(pairs: Sequence[PairSpec], T: int, iters: int, eta: float = 1.0, flags: int = 0,
+                     sync_every: int = 1):
+    """Fixed-step gradient descent on every pair's p0 (updated in place), with
+    the step of a pair halved whenever its cost rises. Returns the plan and the
+    cost history [iters, n_pairs]."""
+    plan = Plan(pairs, T, flags, outputs=("grad", "cost"))
+    n = len(pairs)
+    etas = torch.full((n,), float(eta), dtype=torch.float32, device=plan.device)
+    prev = None
+    hist = []
+    for _ in range(iters):
+        plan.grad()
+        H = plan.out_cost[:, 0].clone()
+        if prev is not None:
+            etas = torch.where(H > prev, etas * 0.5, etas)
+        prev = H
+        hist.append(H)
+        for i, ps in enumerate(pairs):
+            ps.p0.sub_(etas[i] * plan.out_grad[i])
+    return plan, torch.stack(hist) if hist else None

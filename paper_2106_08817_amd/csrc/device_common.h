@@ -1,0 +1,82 @@
+// Device helpers shared by the fused and the per-pair kernels.
+#pragma once
+
+#include "shoot_internal.h"
+
+namespace shoot {
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// Deterministic block sum (fixed shuffle tree, then the NT/64 wave partials in
+// order). The result is valid in thread 0.
+__device__ __forceinline__ float block_sum(float v, float* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += sh[w];
+  }
+  return s;
+}
+
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s = fmaxf(s, sh[w]);
+  }
+  return s;
+}
+
+// Clamped central difference helpers: neighbour offsets along an axis of
+// length n with stride s at index j.
+__device__ __forceinline__ int up(int j, int n, int s) { return j + 1 < n ? s : 0; }
+__device__ __forceinline__ int dn(int j, int s) { return j > 0 ? s : 0; }
+
+// One axis of a foot point in local form: the foot is q + d with d = -dt v.
+// The integer part comes from floor(d) alone, so no absolute coordinate is
+// ever rounded. Clamping follows c = clamp(q + d, 0, n - 1),
+// i = min(floor(c), n - 2), f = c - i; live = 1 iff 0 < q + d < n - 1.
+struct Axis {
+  int i;       // cell index
+  float f;     // fraction in [0, 1]
+  float live;  // 1 where the coordinate is not clamped
+};
+
+__device__ __forceinline__ Axis foot_axis(int q, float d, int n) {
+  d = fminf(fmaxf(d, -1.0e7f), 1.0e7f);
+  const float kf = floorf(d);
+  const float fl = d - kf;            // in [0, 1]; may round to 1 for tiny negative d
+  const int yb = q + (int)kf;
+  Axis a;
+  if (yb < 0) {
+    a.i = 0; a.f = 0.f; a.live = 0.f;
+  } else if (yb >= n - 1) {
+    a.i = n - 2; a.f = 1.f; a.live = 0.f;
+  } else {
+    a.i = yb; a.f = fl;
+    const bool at_lo = (yb == 0) && (fl == 0.f);
+    const bool at_hi = (yb == n - 2) && (fl >= 1.f);
+    a.live = (at_lo || at_hi) ? 0.f : 1.f;
+  }
+  return a;
+}
+
+}  // namespace shoot

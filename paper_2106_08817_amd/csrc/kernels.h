@@ -1,0 +1,58 @@
+// Launchers of the gfx950 kernels (host side of kernels.hip / kernels_unfused.hip).
+#pragma once
+
+#include "shoot_internal.h"
+
+namespace shoot {
+
+struct AdvectArgs {
+  const PairDev* pd;
+  const Tile* tl;
+  const float* V;       // v_t slot [NDIM][N] per pair
+  const float* st;      // (I_t, z_t) slot
+  float* st_out;        // (I_{t+1}, z_{t+1}) slot or null
+  float* ab_out;        // last step: (I_T - J, 0) for the adjoint, or null
+  float* sc_zero;       // last step: scatter accumulator to clear, or null
+  unsigned* dmax;       // per pair and step: max |dt v| (float bits), or null
+  int T, t;
+  float* red_reg;       // first step: per-tile regulariser partials, or null
+  float* red_ssd;       // last step: per-tile data-term partials, or null
+  int last;             // 1 at t = T - 1 (write the outputs)
+};
+
+struct AdjArgs {
+  const PairDev* pd;
+  const Tile* tl;
+  const float* V;       // v_t
+  const float* st;      // (I_t, z_t)
+  const float* ab_in;   // (Ibar_{t+1}, zbar_{t+1})
+  float* sc;            // scatter accumulator (Ibar_t, zbar_t) parts, zeroed before
+  float* db;            // div_bar [N]
+  float* vb;            // vbar [NDIM][N]
+};
+
+struct EpiArgs {
+  const PairDev* pd;
+  const Tile* tl;
+  const float* mb;      // mbar [NDIM][N]
+  const float* st;      // (I_t, z_t)
+  float* sc;            // scatter parts (read, then cleared)
+  float* ab_out;        // (Ibar_t, zbar_t) or null at t = 0
+  int first;            // t == 0: write the gradient
+};
+
+hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s);
+hipError_t launch_init(const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s);
+hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* tl, int nt, size_t lds,
+                        const float* src, float* dst, hipStream_t s);
+hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds,
+                        const float* src, float* dst, const float* extra, hipStream_t s);
+hipError_t launch_advect(int ndim, int nt, const AdvectArgs& a, hipStream_t s);
+hipError_t launch_adv_adj(int ndim, int nt, const AdjArgs& a, hipStream_t s);
+hipError_t launch_divT(int ndim, const PairDev* pd, const Tile* tl, int nt, const float* db, float* vb,
+                       hipStream_t s);
+hipError_t launch_epilogue(int ndim, int nt, const EpiArgs& a, hipStream_t s);
+hipError_t launch_finalize(int npairs, const PairDev* pd, const float* red_reg, const float* red_ssd,
+                           hipStream_t s);
+
+}  // namespace shoot

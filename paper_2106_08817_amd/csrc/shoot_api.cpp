@@ -1,0 +1,679 @@
+// Host runtime behind include/shoot.h: validation, plans (ragged batch
+// descriptors, tile lists, workspace layout, admission waves), the step and
+// checkpoint schedule, and HIP-graph capture.
+#include "shoot.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "unfused.h"
+
+using namespace shoot;
+
+namespace {
+
+thread_local std::string g_err;
+
+shoot_status fail(shoot_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(SHOOT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr long long VOX_ALIGN = 64;             // per-pair voxel offsets are multiples of this
+constexpr long long MAX_VOXELS = 1ll << 28;     // per pair (32-bit index arithmetic in the kernels)
+constexpr size_t XPASS_LDS_CAP = 40 * 1024;     // bytes of LDS per x-pass block (soft)
+constexpr size_t LDS_HARD = 64 * 1024;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+enum Op { OP_FORWARD = 0, OP_COST = 1, OP_GRAD = 2 };
+
+// One admission wave: a subset of the pairs run together.
+struct Wave {
+  std::vector<int> ids;
+  std::vector<PairDev> pdev;
+  std::vector<Tile> te, tx, ty, tz;
+  long long ntot = 0;                // padded voxel total
+  size_t lds_x = 0, lds_y = 0, lds_z = 0;
+  // header offsets (bytes from the workspace base)
+  size_t o_pd = 0, o_te = 0, o_tx = 0, o_ty = 0, o_tz = 0, o_dmax = 0, o_rreg = 0, o_rssd = 0;
+  size_t header_bytes = 0;
+  size_t field_bytes = 0;
+};
+
+struct Fields {  // byte offsets of the field arrays inside the field region
+  size_t st, vs, u, u2, ab, sc, vb, db, end;
+};
+
+// Kernel families, for the profiling statistics.
+enum KId {
+  KI_FILL, KI_INIT, KI_XPASS_M, KI_XPASS_V, KI_SPASS_MID, KI_SPASS_V, KI_SPASS_MBAR,
+  KI_ADVECT, KI_ADV_ADJ, KI_DIVT, KI_EPILOGUE, KI_FINALIZE, KI_COUNT
+};
+const char* const KNAMES[KI_COUNT] = {
+    "fill", "init", "xpass_gradmul", "xpass_plain", "spass_mid", "spass_v", "spass_mbar",
+    "advect", "advect_adjoint", "divT", "epilogue", "finalize"};
+
+// Event pairs around launches; resolved after the stream is synchronised.
+struct Prof {
+  struct Rec { int kid; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  long long launches[KI_COUNT] = {};
+  double ms[KI_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipError_t resolve() {
+    hipError_t err = hipSuccess;
+    for (Rec& r : pending) {
+      float t = 0.f;
+      if (r.a && r.b) {
+        hipError_t e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) err = e;
+        launches[r.kid] += 1;
+        ms[r.kid] += t;
+      }
+      if (r.a) pool.push_back(r.a);
+      if (r.b) pool.push_back(r.b);
+    }
+    pending.clear();
+    return err;
+  }
+  void release() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+struct ProfScope {
+  Prof* p;
+  hipStream_t s;
+  Prof::Rec r;
+  ProfScope(Prof* p_, hipStream_t s_, int kid) : p(p_), s(s_) {
+    if (!p) return;
+    r.kid = kid;
+    r.a = p->get();
+    r.b = p->get();
+    if (r.a) (void)hipEventRecord(r.a, s);
+  }
+  ~ProfScope() {
+    if (!p) return;
+    if (r.b) (void)hipEventRecord(r.b, s);
+    p->pending.push_back(r);
+  }
+};
+
+}  // namespace
+
+struct shoot_plan_s {
+  int npairs = 0, T = 0, ndim = 0, k = 1, nck = 1, nst = 1, nv = 1;
+  uint32_t flags = 0;
+  size_t budget = 0;
+  std::vector<shoot_pair> pairs;
+  std::vector<Wave> waves;
+  size_t header_total = 0, field_max = 0, ws_bytes = 0;
+  std::vector<unsigned char> blob;  // header image uploaded at bind
+  char* ws = nullptr;
+  int device = -1;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  unfused::Plan* uf = nullptr;      // SHOOT_UNFUSED state
+  bool profiling = false;
+  Prof prof;
+};
+
+namespace {
+
+bool fullstore(const shoot_plan_s* p) { return (p->flags & SHOOT_FULL_STORE) != 0; }
+
+Fields field_layout(const shoot_plan_s* p, long long ntot) {
+  const size_t f = sizeof(float);
+  const size_t d = (size_t)p->ndim;
+  Fields F{};
+  size_t o = 0;
+  F.st = o; o = align_up(o + (size_t)p->nst * 2 * ntot * f, ALIGN);
+  F.vs = o; o = align_up(o + (size_t)p->nv * d * ntot * f, ALIGN);
+  F.u = o; o = align_up(o + d * ntot * f, ALIGN);
+  F.u2 = o; o = align_up(o + (p->ndim == 3 ? d * ntot * f : 0), ALIGN);
+  F.ab = o; o = align_up(o + 2 * 2 * ntot * f, ALIGN);
+  F.sc = o; o = align_up(o + 2 * ntot * f, ALIGN);
+  F.vb = o; o = align_up(o + d * ntot * f, ALIGN);
+  F.db = o; o = align_up(o + ntot * f, ALIGN);
+  F.end = o;
+  return F;
+}
+
+long long pair_voxels(const shoot_pair& q) {
+  long long n = 1;
+  for (int a = 0; a < q.ndim; ++a) n *= q.shape[a];
+  return n;
+}
+
+int radius_of(float sigma) { return (int)std::floor(3.0 * (double)sigma); }
+
+void fill_taps(PairDev& P, float sigma) {
+  const int r = P.r;
+  double w[2 * RMAX + 1];
+  double sum = 0.0;
+  for (int k = -r; k <= r; ++k) {
+    w[k + r] = std::exp(-(double)k * k / (2.0 * (double)sigma * (double)sigma));
+    sum += w[k + r];
+  }
+  for (int t = 0; t < WPAD; ++t) P.w[t] = t <= 2 * r ? (float)(w[t] / sum) : 0.f;
+}
+
+size_t xpass_row_bytes(int ndim, int nx, int ntap4) {
+  const int G4 = (nx + 3) / 4;
+  return (size_t)ndim * 4 * (G4 + ntap4) * sizeof(float);
+}
+
+shoot_status validate(const shoot_pair* pairs, int32_t n, int32_t T) {
+  if (!pairs) return fail(SHOOT_E_ARG, "pairs is NULL");
+  if (n < 1) return fail(SHOOT_E_ARG, "n_pairs must be >= 1");
+  if (T < 1) return fail(SHOOT_E_ARG, "T must be >= 1");
+  const int nd = pairs[0].ndim;
+  for (int i = 0; i < n; ++i) {
+    const shoot_pair& q = pairs[i];
+    const std::string at = " (pair " + std::to_string(i) + ")";
+    if (q.ndim != 2 && q.ndim != 3) return fail(SHOOT_E_SHAPE, "ndim must be 2 or 3" + at);
+    if (q.ndim != nd) return fail(SHOOT_E_SHAPE, "all pairs of a plan must share ndim" + at);
+    for (int a = 0; a < q.ndim; ++a)
+      if (q.shape[a] < 2) return fail(SHOOT_E_SHAPE, "every extent must be >= 2" + at);
+    if (pair_voxels(q) > MAX_VOXELS) return fail(SHOOT_E_SHAPE, "pair too large" + at);
+    if (!(q.sigma > 0.f) || !std::isfinite(q.sigma)) return fail(SHOOT_E_ARG, "sigma must be finite and > 0" + at);
+    if (radius_of(q.sigma) > RMAX) return fail(SHOOT_E_ARG, "sigma too large: floor(3 sigma) > 31" + at);
+    if (!(q.rho >= 0.f) || !std::isfinite(q.rho)) return fail(SHOOT_E_ARG, "rho must be finite and >= 0" + at);
+    if (!(q.lambda >= 0.f) || !std::isfinite(q.lambda))
+      return fail(SHOOT_E_ARG, "lambda must be finite and >= 0" + at);
+    if (!q.image) return fail(SHOOT_E_ARG, "image is NULL" + at);
+    if (!q.p0) return fail(SHOOT_E_ARG, "p0 is NULL" + at);
+    const int nx = q.shape[q.ndim - 1];
+    const int ntap4 = (2 * radius_of(q.sigma) + 1 + 3) / 4;
+    if (xpass_row_bytes(q.ndim, nx, ntap4) > LDS_HARD) return fail(SHOOT_E_SHAPE, "last extent too large" + at);
+  }
+  return SHOOT_OK;
+}
+
+// Builds descriptors and tile lists of one wave (header offsets are set later).
+void build_wave(shoot_plan_s* p, Wave& w) {
+  w.pdev.clear(); w.te.clear(); w.tx.clear(); w.ty.clear(); w.tz.clear();
+  long long off = 0;
+  w.lds_x = w.lds_y = w.lds_z = 0;
+  for (size_t li = 0; li < w.ids.size(); ++li) {
+    const shoot_pair& q = p->pairs[w.ids[li]];
+    PairDev P;
+    std::memset(&P, 0, sizeof(P));
+    P.nz = q.ndim == 3 ? q.shape[0] : 1;
+    P.ny = q.shape[q.ndim - 2];
+    P.nx = q.shape[q.ndim - 1];
+    P.r = radius_of(q.sigma);
+    P.ntap4 = (2 * P.r + 1 + 3) / 4;
+    P.N = pair_voxels(q);
+    P.off = off;
+    off += (P.N + VOX_ALIGN - 1) / VOX_ALIGN * VOX_ALIGN;
+    P.rho = q.rho;
+    P.lam = q.lambda;
+    P.dt = (float)(1.0 / (double)p->T);
+    P.S = q.image; P.J = q.target; P.p0 = q.p0;
+    P.outI = q.out_image; P.outZ = q.out_momentum; P.outG = q.out_grad; P.outCost = q.out_cost;
+    fill_taps(P, q.sigma);
+    const int pi = (int)li;
+    // elementwise tiles
+    P.elem_first = (int)w.te.size();
+    for (long long a = 0; a < P.N; a += ELEM)
+      w.te.push_back(Tile{pi, (int)a, (int)std::min<long long>(ELEM, P.N - a), 0});
+    P.elem_count = (int)w.te.size() - P.elem_first;
+    // x-pass tiles: rows of the pair; ~512 groups of four outputs per block,
+    // within the LDS budget
+    const size_t rb = xpass_row_bytes(p->ndim, P.nx, P.ntap4);
+    const int G4 = (P.nx + 3) / 4;
+    int nr = std::max(1, (512 + G4 - 1) / G4);
+    nr = std::min(nr, std::max(1, (int)(XPASS_LDS_CAP / rb)));
+    P.xrows = nr;
+    const int rows = P.nz * P.ny;
+    for (int r0 = 0; r0 < rows; r0 += nr) {
+      const int cnt = std::min(nr, rows - r0);
+      w.tx.push_back(Tile{pi, r0, cnt, 0});
+      w.lds_x = std::max(w.lds_x, rb * (size_t)cnt);
+    }
+    // strided passes
+    const size_t sb = (size_t)(SSEG + 4 * P.ntap4) * 64 * sizeof(float);
+    for (int o = 0; o < P.nz; ++o)
+      for (int x0 = 0; x0 < P.nx; x0 += 64)
+        for (int s0 = 0; s0 < P.ny; s0 += SSEG) w.ty.push_back(Tile{pi, x0, o, s0});
+    w.lds_y = std::max(w.lds_y, sb);
+    if (p->ndim == 3) {
+      for (int o = 0; o < P.ny; ++o)
+        for (int x0 = 0; x0 < P.nx; x0 += 64)
+          for (int s0 = 0; s0 < P.nz; s0 += SSEG) w.tz.push_back(Tile{pi, x0, o, s0});
+      w.lds_z = std::max(w.lds_z, sb);
+    }
+    w.pdev.push_back(P);
+  }
+  w.ntot = off;
+  w.field_bytes = field_layout(p, w.ntot).end;
+}
+
+size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
+  size_t o = base;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, ALIGN); return r; };
+  w.o_pd = take(w.pdev.size() * sizeof(PairDev));
+  w.o_te = take(w.te.size() * sizeof(Tile));
+  w.o_tx = take(w.tx.size() * sizeof(Tile));
+  w.o_ty = take(w.ty.size() * sizeof(Tile));
+  w.o_tz = take(w.tz.size() * sizeof(Tile));
+  w.o_dmax = take(w.pdev.size() * (size_t)p->T * sizeof(unsigned));
+  w.o_rreg = take(w.te.size() * sizeof(float));
+  w.o_rssd = take(w.te.size() * sizeof(float));
+  w.header_bytes = o - base;
+  return o;
+}
+
+// -------------------------------------------------------------------- schedule
+
+struct Ctx {
+  shoot_plan_s* p;
+  Wave* w;
+  hipStream_t s;
+  const PairDev* pd;
+  const Tile *te, *tx, *ty, *tz;
+  int nte, ntx, nty, ntz;
+  unsigned* dmax;
+  float *rreg, *rssd;
+  float *st, *vs, *u, *u2, *ab, *sc, *vb, *db;
+  long long ntot;
+  Prof* prof;
+};
+
+Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
+  Ctx c{};
+  c.p = p; c.w = &w; c.s = s;
+  char* b = p->ws;
+  c.pd = (const PairDev*)(b + w.o_pd);
+  c.te = (const Tile*)(b + w.o_te); c.nte = (int)w.te.size();
+  c.tx = (const Tile*)(b + w.o_tx); c.ntx = (int)w.tx.size();
+  c.ty = (const Tile*)(b + w.o_ty); c.nty = (int)w.ty.size();
+  c.tz = (const Tile*)(b + w.o_tz); c.ntz = (int)w.tz.size();
+  c.dmax = (unsigned*)(b + w.o_dmax);
+  c.rreg = (float*)(b + w.o_rreg);
+  c.rssd = (float*)(b + w.o_rssd);
+  char* f = b + p->header_total;
+  const Fields F = field_layout(p, w.ntot);
+  c.st = (float*)(f + F.st); c.vs = (float*)(f + F.vs); c.u = (float*)(f + F.u); c.u2 = (float*)(f + F.u2);
+  c.ab = (float*)(f + F.ab); c.sc = (float*)(f + F.sc); c.vb = (float*)(f + F.vb); c.db = (float*)(f + F.db);
+  c.ntot = w.ntot;
+  return c;
+}
+
+int st_slot(const shoot_plan_s* p, int t) {
+  if (fullstore(p)) return t;
+  return (t % p->k == 0) ? t / p->k : p->nck + (t % p->k) - 1;
+}
+int v_slot(const shoot_plan_s* p, int t) { return fullstore(p) ? t : t % p->k; }
+float* ST(const Ctx& c, int t) { return c.st + (size_t)st_slot(c.p, t) * 2 * c.ntot; }
+float* VS(const Ctx& c, int t) { return c.vs + (size_t)v_slot(c.p, t) * c.p->ndim * c.ntot; }
+float* AB(const Ctx& c, int t) { return c.ab + (size_t)(t & 1) * 2 * c.ntot; }
+
+#define LAUNCH(kid, expr)                       \
+  do {                                          \
+    ProfScope ps_(c.prof, c.s, kid);            \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return e_;            \
+  } while (0)
+
+// v_t = -G (z_t grad I_t) into the v slot of t.
+hipError_t velocity(const Ctx& c, int t) {
+  const int nd = c.p->ndim;
+  LAUNCH(KI_XPASS_M, launch_xpass(nd, true, c.pd, c.tx, c.ntx, c.w->lds_x, ST(c, t), c.u, c.s));
+  if (nd == 2) {
+    LAUNCH(KI_SPASS_V, launch_spass(2, false, 1, c.pd, c.ty, c.nty, c.w->lds_y, c.u, VS(c, t), nullptr, c.s));
+    return hipSuccess;
+  }
+  LAUNCH(KI_SPASS_MID, launch_spass(3, false, 0, c.pd, c.ty, c.nty, c.w->lds_y, c.u, c.u2, nullptr, c.s));
+  LAUNCH(KI_SPASS_V, launch_spass(3, true, 1, c.pd, c.tz, c.ntz, c.w->lds_z, c.u2, VS(c, t), nullptr, c.s));
+  return hipSuccess;
+}
+
+// One forward step t -> t + 1. `store` writes state t + 1 to its slot.
+hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
+  hipError_t e = velocity(c, t);
+  if (e != hipSuccess) return e;
+  const int T = c.p->T;
+  AdvectArgs a{};
+  a.pd = c.pd; a.tl = c.te; a.V = VS(c, t); a.st = ST(c, t);
+  a.st_out = (store && t + 1 < T) ? ST(c, t + 1) : nullptr;
+  a.T = T; a.t = t;
+  a.dmax = first_pass ? c.dmax : nullptr;
+  a.last = (first_pass && t == T - 1) ? 1 : 0;
+  a.red_reg = (first_pass && t == 0) ? c.rreg : nullptr;
+  a.red_ssd = (first_pass && t == T - 1) ? c.rssd : nullptr;
+  if (a.last && op == OP_GRAD) { a.ab_out = AB(c, T); a.sc_zero = c.sc; }
+  LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.nte, a, c.s));
+  return hipSuccess;
+}
+
+hipError_t run_forward(const Ctx& c, int op) {
+  const int T = c.p->T;
+  LAUNCH(KI_FILL, launch_fill_u32(c.dmax, (long long)c.w->pdev.size() * T, 0u, c.s));
+  LAUNCH(KI_INIT, launch_init(c.pd, c.te, c.nte, ST(c, 0), c.s));
+  for (int t = 0; t < T; ++t) {
+    hipError_t e = fwd_step(c, t, true, op, true);
+    if (e != hipSuccess) return e;
+  }
+  LAUNCH(KI_FINALIZE, launch_finalize((int)c.w->pdev.size(), c.pd, c.rreg, c.rssd, c.s));
+  return hipSuccess;
+}
+
+// Adjoint of step t: (Ibar_{t+1}, zbar_{t+1}) in AB(t+1) -> AB(t) (or dH/dp0 at t = 0).
+hipError_t bwd_step(const Ctx& c, int t) {
+  const int nd = c.p->ndim;
+  AdjArgs a{};
+  a.pd = c.pd; a.tl = c.te; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
+  a.sc = c.sc; a.db = c.db; a.vb = c.vb;
+  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.nte, a, c.s));
+  LAUNCH(KI_DIVT, launch_divT(nd, c.pd, c.te, c.nte, c.db, c.vb, c.s));
+  // mbar = -G vbar (+ -2 lambda v_0 at t = 0), written back into vb
+  LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.w->lds_x, c.vb, c.u, c.s));
+  const float* extra = t == 0 ? VS(c, 0) : nullptr;
+  if (nd == 2) {
+    LAUNCH(KI_SPASS_MBAR, launch_spass(2, false, 2, c.pd, c.ty, c.nty, c.w->lds_y, c.u, c.vb, extra, c.s));
+  } else {
+    LAUNCH(KI_SPASS_MID, launch_spass(3, false, 0, c.pd, c.ty, c.nty, c.w->lds_y, c.u, c.u2, nullptr, c.s));
+    LAUNCH(KI_SPASS_MBAR, launch_spass(3, true, 2, c.pd, c.tz, c.ntz, c.w->lds_z, c.u2, c.vb, extra, c.s));
+  }
+  EpiArgs ep{};
+  ep.pd = c.pd; ep.tl = c.te; ep.mb = c.vb; ep.st = ST(c, t); ep.sc = c.sc;
+  ep.ab_out = t > 0 ? AB(c, t) : nullptr;
+  ep.first = t == 0 ? 1 : 0;
+  LAUNCH(KI_EPILOGUE, launch_epilogue(nd, c.nte, ep, c.s));
+  return hipSuccess;
+}
+
+hipError_t run_grad(const Ctx& c) {
+  hipError_t e = run_forward(c, OP_GRAD);
+  if (e != hipSuccess) return e;
+  const shoot_plan_s* p = c.p;
+  const int T = p->T;
+  const int k = fullstore(p) ? T : p->k;
+  const int nseg = (T + k - 1) / k;
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int t0 = s * k, t1 = std::min(T, t0 + k);
+    if (s != nseg - 1) {
+      // restore states t0+1 .. t1-1 and velocities t0 .. t1-1 from checkpoint t0
+      for (int t = t0; t < t1; ++t) {
+        e = fwd_step(c, t, t + 1 < t1, OP_GRAD, false);
+        if (e != hipSuccess) return e;
+      }
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+      e = bwd_step(c, t);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue(shoot_plan_s* p, int op, hipStream_t s) {
+  for (Wave& w : p->waves) {
+    Ctx c = make_ctx(p, w, s);
+    c.prof = p->profiling ? &p->prof : nullptr;
+    hipError_t e = (op == OP_GRAD) ? run_grad(c) : run_forward(c, op);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void drop_graphs(shoot_plan_s* p) {
+  for (auto& g : p->graph)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+shoot_status execute(shoot_plan_s* p, int op, void* stream) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (!p->ws) return fail(SHOOT_E_STATE, "plan is not bound to a workspace");
+  for (int i = 0; i < p->npairs; ++i) {
+    const shoot_pair& q = p->pairs[i];
+    if (op != OP_FORWARD && !q.target) return fail(SHOOT_E_ARG, "target is NULL (pair " + std::to_string(i) + ")");
+    if (op == OP_COST && !q.out_cost) return fail(SHOOT_E_ARG, "out_cost is NULL (pair " + std::to_string(i) + ")");
+    if (op == OP_GRAD && !q.out_grad) return fail(SHOOT_E_ARG, "out_grad is NULL (pair " + std::to_string(i) + ")");
+  }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != p->device) return fail(SHOOT_E_STATE, "current device differs from the device the plan was bound on");
+  hipStream_t s = (hipStream_t)stream;
+  if (p->uf) {
+    hipError_t e = unfused::run(p->uf, op, s);
+    if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("unfused path: ") + hipGetErrorString(e));
+    return SHOOT_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s) HIPCHK(hipStreamIsCapturing(s, &cs));
+  if (p->profiling) {
+    if (cs != hipStreamCaptureStatusNone) return fail(SHOOT_E_STATE, "profiling cannot run under stream capture");
+    hipError_t e = enqueue(p, op, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipError_t e3 = p->prof.resolve();
+    if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e2));
+    if (e3 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e3));
+    return SHOOT_OK;
+  }
+  if ((p->flags & SHOOT_NO_GRAPH) || cs != hipStreamCaptureStatusNone) {
+    hipError_t e = enqueue(p, op, s);
+    if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SHOOT_OK;
+  }
+  if (!p->graph[op]) {
+    HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+    hipError_t e = enqueue(p, op, p->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(SHOOT_E_HIP, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    p->graph[op] = x;
+  }
+  HIPCHK(hipGraphLaunch(p->graph[op], s));
+  return SHOOT_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+// The library is built with hidden visibility; only this block is exported.
+#pragma GCC visibility push(default)
+extern "C" {
+
+const char* shoot_version(void) { return "shoot 1.0 (gfx950)"; }
+
+const char* shoot_last_error(void) { return g_err.c_str(); }
+
+shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t T, uint32_t flags,
+                               size_t budget_bytes, shoot_plan* out) {
+  if (!out) return fail(SHOOT_E_ARG, "out is NULL");
+  *out = nullptr;
+  const uint32_t known = SHOOT_FULL_STORE | SHOOT_UNFUSED | SHOOT_NO_GRAPH | SHOOT_FORCE_GLOBAL_SCATTER;
+  if (flags & ~known) return fail(SHOOT_E_ARG, "unknown flag bits");
+  shoot_status st = validate(pairs, n_pairs, T);
+  if (st != SHOOT_OK) return st;
+  shoot_plan_s* p = new (std::nothrow) shoot_plan_s();
+  if (!p) return fail(SHOOT_E_ARG, "out of host memory");
+  p->npairs = n_pairs;
+  p->T = T;
+  p->ndim = pairs[0].ndim;
+  p->flags = flags;
+  p->budget = budget_bytes;
+  p->pairs.assign(pairs, pairs + n_pairs);
+  p->k = std::max(1, (int)std::ceil(std::sqrt((double)T) - 1e-9));
+  while ((long long)p->k * p->k < T) ++p->k;
+  p->nck = (T + p->k - 1) / p->k;
+  if (fullstore(p)) {
+    p->nst = T;
+    p->nv = T;
+  } else {
+    p->nst = p->nck + p->k - 1;
+    p->nv = p->k;
+  }
+  if (flags & SHOOT_UNFUSED) {
+    p->uf = unfused::create(p->pairs.data(), n_pairs, T);
+    if (!p->uf) { delete p; return fail(SHOOT_E_ARG, "out of host memory"); }
+    p->ws_bytes = unfused::workspace_bytes(p->uf);
+    *out = p;
+    g_err.clear();
+    return SHOOT_OK;
+  }
+  // admission: first-fit in order into waves whose field region fits the budget
+  std::vector<Wave> waves;
+  Wave cur;
+  for (int i = 0; i < n_pairs; ++i) {
+    Wave trial = cur;
+    trial.ids.push_back(i);
+    build_wave(p, trial);
+    if (budget_bytes && !cur.ids.empty() && trial.field_bytes > budget_bytes) {
+      waves.push_back(cur);
+      cur = Wave();
+      cur.ids.push_back(i);
+      build_wave(p, cur);
+    } else {
+      cur = trial;
+    }
+    if (budget_bytes && cur.ids.size() == 1 && cur.field_bytes > budget_bytes) {
+      delete p;
+      return fail(SHOOT_E_BUDGET, "pair " + std::to_string(i) + " alone needs " +
+                                      std::to_string(cur.field_bytes) + " bytes, over the budget");
+    }
+  }
+  waves.push_back(cur);
+  p->waves = waves;
+  size_t o = 0;
+  for (Wave& w : p->waves) {
+    o = header_size(p, w, o);
+    p->field_max = std::max(p->field_max, w.field_bytes);
+  }
+  p->header_total = align_up(o, ALIGN);
+  p->ws_bytes = p->header_total + p->field_max;
+  // host image of the header
+  p->blob.assign(p->header_total, 0);
+  for (Wave& w : p->waves) {
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+      if (bytes) std::memcpy(p->blob.data() + off, src, bytes);
+    };
+    put(w.o_pd, w.pdev.data(), w.pdev.size() * sizeof(PairDev));
+    put(w.o_te, w.te.data(), w.te.size() * sizeof(Tile));
+    put(w.o_tx, w.tx.data(), w.tx.size() * sizeof(Tile));
+    put(w.o_ty, w.ty.data(), w.ty.size() * sizeof(Tile));
+    put(w.o_tz, w.tz.data(), w.tz.size() * sizeof(Tile));
+  }
+  *out = p;
+  g_err.clear();
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_workspace_bytes(shoot_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(SHOOT_E_ARG, "NULL argument");
+  *bytes = p->ws_bytes;
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_waves(shoot_plan p, int32_t* waves) {
+  if (!p || !waves) return fail(SHOOT_E_ARG, "NULL argument");
+  *waves = p->uf ? p->npairs : (int32_t)p->waves.size();
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* stream) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (!workspace && p->ws_bytes) return fail(SHOOT_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace) % ALIGN) return fail(SHOOT_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < p->ws_bytes)
+    return fail(SHOOT_E_WORKSPACE, "workspace too small: need " + std::to_string(p->ws_bytes) + " bytes");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  drop_graphs(p);
+  if (p->cap && dev != p->device) {
+    (void)hipStreamDestroy(p->cap);
+    p->cap = nullptr;
+  }
+  if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+  p->device = dev;
+  p->ws = (char*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  if (p->uf) {
+    hipError_t e = unfused::bind(p->uf, p->ws, s);
+    if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("unfused bind: ") + hipGetErrorString(e));
+    return SHOOT_OK;
+  }
+  if (p->header_total) HIPCHK(hipMemcpyAsync(p->ws, p->blob.data(), p->header_total, hipMemcpyHostToDevice, s));
+  return SHOOT_OK;
+}
+
+shoot_status shoot_autotune(shoot_plan p, void* stream) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (!p->ws) return fail(SHOOT_E_STATE, "plan is not bound to a workspace");
+  (void)stream;
+  return SHOOT_OK;
+}
+
+shoot_status shoot_forward(shoot_plan p, void* stream) { return execute(p, OP_FORWARD, stream); }
+shoot_status shoot_cost(shoot_plan p, void* stream) { return execute(p, OP_COST, stream); }
+shoot_status shoot_grad_p0(shoot_plan p, void* stream) { return execute(p, OP_GRAD, stream); }
+
+shoot_status shoot_plan_set_profiling(shoot_plan p, int32_t enable) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (p->uf && enable) return fail(SHOOT_E_ARG, "profiling is not available on the unfused path");
+  p->profiling = enable != 0;
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_reset_stats(shoot_plan p) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  for (int i = 0; i < KI_COUNT; ++i) { p->prof.launches[i] = 0; p->prof.ms[i] = 0.0; }
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_kernel_stats(shoot_plan p, int32_t index, const char** name, int64_t* launches,
+                                     double* total_ms) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (index < 0 || index >= KI_COUNT) return fail(SHOOT_E_ARG, "kernel index out of range");
+  if (name) *name = KNAMES[index];
+  if (launches) *launches = p->prof.launches[index];
+  if (total_ms) *total_ms = p->prof.ms[index];
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_destroy(shoot_plan p) {
+  if (!p) return SHOOT_OK;
+  drop_graphs(p);
+  p->prof.release();
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->uf) unfused::destroy(p->uf);
+  delete p;
+  return SHOOT_OK;
+}
+
+}  // extern "C"
+#pragma GCC visibility pop

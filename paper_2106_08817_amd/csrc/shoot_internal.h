@@ -1,0 +1,68 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shoot {
+
+// Largest Gaussian radius supported: floor(3 sigma) <= RMAX.
+constexpr int RMAX = 31;
+// Padded tap table: taps t = 0..2r hold w(t - r), the rest are zero, padded to
+// a multiple of 4 so the tap loops run in blocks of four.
+constexpr int WPAD = 4 * ((2 * RMAX + 1 + 3) / 4);   // 64
+
+// Threads per block for every kernel.
+constexpr int NT = 256;
+// Voxels per elementwise tile (each thread handles ELEM / NT of them).
+constexpr int ELEM = 1024;
+// Strided-pass tile: 64 lanes along x, NT/64 waves along the pass axis, each
+// thread produces SRB consecutive outputs along it.
+constexpr int SRB = 16;
+constexpr int SSEG = (NT / 64) * SRB;                  // 64 outputs per tile
+
+// Per-pair descriptor, resident in the workspace. Geometry is stored as
+// (nz, ny, nx) with nz = 1 in 2-D; channel / axis c of a vector field follows
+// the array's own axis order (2-D: c0 = y, c1 = x; 3-D: c0 = z, c1 = y, c2 = x).
+struct alignas(16) PairDev {
+  int nz, ny, nx;
+  int r;          // Gaussian radius floor(3 sigma)
+  int ntap4;      // ceil((2r + 1) / 4)
+  int xrows;      // rows per x-pass tile for this pair
+  int elem_first; // index of this pair's first elementwise tile
+  int elem_count; // number of elementwise tiles of this pair
+  long long off;  // voxel offset of the pair in the batch
+  long long N;    // voxels
+  float rho, lam, dt, pad_;
+  const float* S;
+  const float* J;
+  const float* p0;
+  float* outI;
+  float* outZ;
+  float* outG;
+  float* outCost;
+  long long reserved_;
+  float w[WPAD];  // padded taps (see WPAD)
+};
+static_assert(sizeof(long long) == 8 && sizeof(void*) == 8, "LP64 expected");
+static_assert(__builtin_offsetof(PairDev, w) % 16 == 0, "taps must be 16-byte aligned");
+
+// Tile entry of a launch list. Meaning of a/b/c per kernel family:
+//   elementwise: a = first voxel, b = voxel count
+//   x-pass     : a = first row (rows are (z, y) flattened), b = row count
+//   y/z-pass   : a = first x, b = index along the third axis, c = first output
+struct alignas(16) Tile {
+  int pair, a, b, c;
+};
+
+// Maps blockIdx.x to a tile index so that each XCD (blocks are dealt to the 8
+// XCDs round-robin) receives one contiguous run of the tile list: neighbouring
+// tiles share halos and then share an L2.
+__device__ __forceinline__ int xcd_tile(int nb) {
+  const int b = blockIdx.x;
+  const int q = nb >> 3, rem = nb & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
+}  // namespace shoot

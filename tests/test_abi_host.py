@@ -1,0 +1,128 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/shoot.h declares, and validates plans (no GPU call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2106_08817_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shoot.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(shoot_\w+)\s*\(", src, flags=re.M))
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    declared = header_functions()
+    assert declared == set(_lib.EXPORTS), declared ^ set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.shoot_version()
+
+
+FAKE = 0x7F0000000000  # never dereferenced: plan creation is host-only
+
+
+def pair(ndim=2, shape=(32, 40), rho=0.5, sigma=2.0, lam=0.01, image=FAKE, p0=FAKE + 4096, target=FAKE + 8192):
+    p = _lib.ShootPair()
+    p.ndim = ndim
+    for a in range(3):
+        p.shape[a] = shape[a] if a < len(shape) else 0
+    p.rho, p.sigma, p.lambda_ = rho, sigma, lam
+    p.image, p.p0, p.target = image, p0, target
+    p.out_grad = FAKE + 12288
+    p.out_cost = FAKE + 16384
+    return p
+
+
+def create(pairs, T=10, flags=0, budget=0):
+    lib = _lib.load()
+    arr = (_lib.ShootPair * len(pairs))(*pairs)
+    h = ctypes.c_void_p(123)
+    st = lib.shoot_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(pairs), T, flags, budget, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,T,status", [
+    (dict(ndim=4), 10, _lib.SHOOT_E_SHAPE),
+    (dict(shape=(1, 40)), 10, _lib.SHOOT_E_SHAPE),
+    (dict(sigma=0.0), 10, _lib.SHOOT_E_ARG),
+    (dict(sigma=float("nan")), 10, _lib.SHOOT_E_ARG),
+    (dict(sigma=11.0), 10, _lib.SHOOT_E_ARG),
+    (dict(rho=-0.1), 10, _lib.SHOOT_E_ARG),
+    (dict(lam=-1.0), 10, _lib.SHOOT_E_ARG),
+    (dict(image=None), 10, _lib.SHOOT_E_ARG),
+    (dict(p0=None), 10, _lib.SHOOT_E_ARG),
+    (dict(), 0, _lib.SHOOT_E_ARG),
+    (dict(ndim=3, shape=(4, 5, 40000)), 10, _lib.SHOOT_E_SHAPE),
+])
+def test_plan_validation(kw, T, status):
+    st, h = create([pair(**kw)], T=T)
+    assert st == status
+    assert h.value is None
+    assert len(_lib.load().shoot_last_error()) > 0
+
+
+def test_mixed_ndim_and_unknown_flags_rejected():
+    st, _ = create([pair(), pair(ndim=3, shape=(8, 8, 8))])
+    assert st == _lib.SHOOT_E_SHAPE
+    st, _ = create([pair()], flags=1 << 20)
+    assert st == _lib.SHOOT_E_ARG
+
+
+def test_plan_sizes_waves_and_unbound_execution():
+    lib = _lib.load()
+    st, h = create([pair(shape=(96, 128)), pair(shape=(240, 320), sigma=5.5)], T=20)
+    assert st == _lib.SHOOT_OK
+    n = ctypes.c_size_t()
+    assert lib.shoot_plan_workspace_bytes(h, ctypes.byref(n)) == _lib.SHOOT_OK
+    ck = n.value
+    w = ctypes.c_int32()
+    assert lib.shoot_plan_waves(h, ctypes.byref(w)) == _lib.SHOOT_OK and w.value == 1
+    # execution before bind is refused before any device work
+    assert lib.shoot_grad_p0(h, None) == _lib.SHOOT_E_STATE
+    # bind refuses missing / misaligned / short workspaces before any HIP call
+    assert lib.shoot_plan_bind(h, None, n.value, None) == _lib.SHOOT_E_WORKSPACE
+    assert lib.shoot_plan_bind(h, FAKE + 4, n.value, None) == _lib.SHOOT_E_WORKSPACE
+    assert lib.shoot_plan_bind(h, FAKE, n.value - 1, None) == _lib.SHOOT_E_WORKSPACE
+    assert lib.shoot_plan_destroy(h) == _lib.SHOOT_OK
+    # full store keeps all T states: more memory than sqrt(T) checkpoints
+    st, h = create([pair(shape=(96, 128)), pair(shape=(240, 320), sigma=5.5)], T=20, flags=_lib.SHOOT_FULL_STORE)
+    assert lib.shoot_plan_workspace_bytes(h, ctypes.byref(n)) == _lib.SHOOT_OK
+    assert n.value > ck
+    lib.shoot_plan_destroy(h)
+    assert lib.shoot_plan_destroy(None) == _lib.SHOOT_OK
+
+
+def test_budget_splits_into_waves():
+    lib = _lib.load()
+    pairs = [pair(shape=(128, 128)) for _ in range(6)]
+    st, h = create(pairs, T=9)
+    n1 = ctypes.c_size_t()
+    lib.shoot_plan_workspace_bytes(h, ctypes.byref(n1))
+    lib.shoot_plan_destroy(h)
+    st, h = create(pairs, T=9, budget=n1.value // 2)
+    assert st == _lib.SHOOT_OK
+    w = ctypes.c_int32()
+    lib.shoot_plan_waves(h, ctypes.byref(w))
+    assert w.value >= 2
+    n2 = ctypes.c_size_t()
+    lib.shoot_plan_workspace_bytes(h, ctypes.byref(n2))
+    assert n2.value < n1.value
+    lib.shoot_plan_destroy(h)
+    st, h = create(pairs, T=9, budget=1024)
+    assert st == _lib.SHOOT_E_BUDGET
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_LIB", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.load()
