@@ -5,6 +5,9 @@
 
 namespace shoot {
 
+// Native 4-float vector: LDS loads of it become one aligned ds_read_b128.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

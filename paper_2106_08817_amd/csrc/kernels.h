@@ -22,23 +22,28 @@ struct AdvectArgs {
 
 struct AdjArgs {
   const PairDev* pd;
-  const Tile* tl;
-  const float* V;       // v_t
-  const float* st;      // (I_t, z_t)
-  const float* ab_in;   // (Ibar_{t+1}, zbar_{t+1})
-  float* sc;            // scatter accumulator (Ibar_t, zbar_t) parts, zeroed before
-  float* db;            // div_bar [N]
-  float* vb;            // vbar [NDIM][N]
+  const Tile* tl;        // adjoint tiles (x0, y0, z0)
+  const float* V;        // v_t
+  const float* st;       // (I_t, z_t)
+  const float* ab_in;    // (Ibar_{t+1}, zbar_{t+1})
+  float* sc;             // scatter parts of (Ibar_t, zbar_t)
+  float* vb;             // vbar [NDIM][N]
+  const unsigned* dmax;  // per pair and step: max |dt v| (float bits)
+  int T, t;
+  int force_global;      // scatter through global atomics regardless of D
 };
 
 struct EpiArgs {
   const PairDev* pd;
   const Tile* tl;
-  const float* mb;      // mbar [NDIM][N]
-  const float* st;      // (I_t, z_t)
-  float* sc;            // scatter parts (read, then cleared)
-  float* ab_out;        // (Ibar_t, zbar_t) or null at t = 0
-  int first;            // t == 0: write the gradient
+  const float* mb;       // mbar [NDIM][N]
+  const float* st;       // (I_t, z_t)
+  float* sc;             // scatter parts (read; cleared when step t - 1 scatters globally)
+  float* ab_out;         // (Ibar_t, zbar_t) or null at t = 0
+  const unsigned* dmax;  // per pair and step: max |dt v| (float bits)
+  int T, t;
+  int force_global;
+  int first;             // t == 0: write the gradient
 };
 
 hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s);
@@ -49,8 +54,6 @@ hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const
                         const float* src, float* dst, const float* extra, hipStream_t s);
 hipError_t launch_advect(int ndim, int nt, const AdvectArgs& a, hipStream_t s);
 hipError_t launch_adv_adj(int ndim, int nt, const AdjArgs& a, hipStream_t s);
-hipError_t launch_divT(int ndim, const PairDev* pd, const Tile* tl, int nt, const float* db, float* vb,
-                       hipStream_t s);
 hipError_t launch_epilogue(int ndim, int nt, const EpiArgs& a, hipStream_t s);
 hipError_t launch_finalize(int npairs, const PairDev* pd, const float* red_reg, const float* red_ssd,
                            hipStream_t s);

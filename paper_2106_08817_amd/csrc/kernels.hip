@@ -10,8 +10,8 @@
 //                      z' = zh (1 - dt div v); cost partials at the first and
 //                      last step
 // Adjoint step (transpose of the above, in reverse):
-//   k_adv_adj + k_divT    scatter-add of the interpolation transpose, the
-//                         foot-point cotangent and div^T
+//   k_adv_adj_tile        tile-owned transpose of the interpolation (LDS
+//                         accumulation), foot-point cotangent and div^T
 //   k_xpass<plain>, k_spass  G is symmetric, so the same passes smooth vbar
 //   k_epilogue            transpose of m = z D I
 #include "kernels.h"
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(NT) void k_init(const PairDev* __restrict__ pd, con
 template <int NDIM, bool GRADMUL>
 __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst) {
-  extern __shared__ float4 smem4[];
+  extern __shared__ vf4 smem4[];
   float* lds = reinterpret_cast<float*>(smem4);
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
@@ -65,40 +65,54 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   const int row0 = t.a, nrows = t.b;
   const int plane = nrows * L;
 
+  // fill: one wave per row, lanes along the row (every load of a row is
+  // independent, so the unrolled column loop keeps several in flight)
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
   if (GRADMUL) {
-    const float* I = src + 2 * P.off;
-    const float* Z = I + N;
-    for (int li = threadIdx.x; li < plane; li += NT) {
-      const int rl = li / L;
-      const int x = li - rl * L - r;
-      float m[NDIM];
-#pragma unroll
-      for (int c = 0; c < NDIM; ++c) m[c] = 0.f;
-      if (x >= 0 && x < nx) {
-        const int row = row0 + rl;
-        const int y = row % ny;
-        const int idx = row * nx + x;
-        const float zq = Z[idx];
-        m[NDIM - 1] = zq * 0.5f * (I[idx + up(x, nx, 1)] - I[idx - dn(x, 1)]);
-        m[NDIM - 2] = zq * 0.5f * (I[idx + up(y, ny, nx)] - I[idx - dn(y, nx)]);
-        if (NDIM == 3) {
-          const int z = row / ny;
-          const int s = ny * nx;
-          m[0] = zq * 0.5f * (I[idx + up(z, nz, s)] - I[idx - dn(z, s)]);
-        }
+    const float* __restrict__ I = src + 2 * P.off;
+    const float* __restrict__ Z = I + N;
+    for (int rl = wv; rl < nrows; rl += NT / 64) {
+      const int row = row0 + rl;
+      const int y = row % ny;
+      const int rbase = row * nx;
+      const int yu = up(y, ny, nx), yd = dn(y, nx);
+      int zu = 0, zd = 0;
+      if (NDIM == 3) {
+        const int z = row / ny;
+        zu = up(z, nz, ny * nx);
+        zd = dn(z, ny * nx);
       }
+      float* Lrow = lds + rl * L;
+#pragma unroll 4
+      for (int col = lane; col < L; col += 64) {
+        const int x = col - r;
+        float m[NDIM];
 #pragma unroll
-      for (int c = 0; c < NDIM; ++c) lds[c * plane + li] = m[c];
+        for (int c = 0; c < NDIM; ++c) m[c] = 0.f;
+        if (x >= 0 && x < nx) {
+          const int idx = rbase + x;
+          const float zq = 0.5f * Z[idx];
+          m[NDIM - 1] = zq * (I[idx + up(x, nx, 1)] - I[idx - dn(x, 1)]);
+          m[NDIM - 2] = zq * (I[idx + yu] - I[idx - yd]);
+          if (NDIM == 3) m[0] = zq * (I[idx + zu] - I[idx - zd]);
+        }
+#pragma unroll
+        for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = m[c];
+      }
     }
   } else {
-    const float* F = src + NDIM * P.off;
-    for (int li = threadIdx.x; li < plane; li += NT) {
-      const int rl = li / L;
-      const int x = li - rl * L - r;
-      const bool in = (x >= 0 && x < nx);
-      const int idx = (row0 + rl) * nx + x;
+    const float* __restrict__ F = src + NDIM * P.off;
+    for (int rl = wv; rl < nrows; rl += NT / 64) {
+      const int rbase = (row0 + rl) * nx;
+      float* Lrow = lds + rl * L;
+#pragma unroll 4
+      for (int col = lane; col < L; col += 64) {
+        const int x = col - r;
+        const bool in = (x >= 0 && x < nx);
 #pragma unroll
-      for (int c = 0; c < NDIM; ++c) lds[c * plane + li] = in ? F[c * N + idx] : 0.f;
+        for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = in ? F[c * N + rbase + x] : 0.f;
+      }
     }
   }
   __syncthreads();
@@ -112,11 +126,13 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
     const int obase = (row0 + rl) * nx + x;
 #pragma unroll
     for (int c = 0; c < NDIM; ++c) {
-      const float4* R4 = reinterpret_cast<const float4*>(lds + c * plane + rl * L + x);
+      // row offsets are multiples of four floats: index the LDS as float4 so
+      // the reads are aligned ds_read_b128 (consecutive lanes, consecutive 16 B)
+      const vf4* R4 = smem4 + ((c * plane + rl * L + x) >> 2);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-      float4 lo = R4[0];
+      vf4 lo = R4[0];
       for (int b = 0; b < ntap4; ++b) {
-        const float4 hi = R4[b + 1];
+        const vf4 hi = R4[b + 1];
         const float4 w = W4[b];
         a0 = fmaf(w.x, lo.x, a0); a1 = fmaf(w.x, lo.y, a1); a2 = fmaf(w.x, lo.z, a2); a3 = fmaf(w.x, lo.w, a3);
         a0 = fmaf(w.y, lo.y, a0); a1 = fmaf(w.y, lo.z, a1); a2 = fmaf(w.y, lo.w, a2); a3 = fmaf(w.y, hi.x, a3);
@@ -142,16 +158,16 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
 // ----------------------------------------------------------------------------
 //
 // A tile is 64 consecutive x (one per lane) x SSEG outputs along the pass axis
-// at one index of the third axis. Channels are processed one after another
-// through one LDS buffer of (SSEG + 4 ntap4) rows x 64 floats; LDS row j holds
-// the input at s = s0 - r + j. Each thread produces SRB consecutive outputs.
+// at one index of the third axis, for the channel blockIdx.y. The input is
+// staged in LDS as (SSEG + 4 ntap4) rows x 64 floats; LDS row j holds the
+// input at s = s0 - r + j. Each thread produces SRB consecutive outputs.
 // MODE 0: plain pass. MODE 1: negated (v = -G m). MODE 2: negated, plus
 // extra_scale * extra (the regulariser's cotangent at t = 0).
 template <int NDIM, bool PASSZ, int MODE>
 __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst,
                                               const float* __restrict__ extra) {
-  extern __shared__ float4 smem4[];
+  extern __shared__ vf4 smem4[];
   float* lds = reinterpret_cast<float*>(smem4);
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
@@ -174,8 +190,10 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
   const bool xin = x < nx;
 
-  for (int c = 0; c < NDIM; ++c) {
+  {
+    const int c = blockIdx.y;  // one channel per block
     const float* Fc = F + c * N;
+#pragma unroll 8
     for (int j = wv; j < rows; j += NT / 64) {
       const int s = s0 - r + j;
       lds[j * 64 + lane] = (xin && s >= 0 && s < ns) ? Fc[base + s * ss] : 0.f;
@@ -211,7 +229,6 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
         }
       }
     }
-    __syncthreads();
   }
 }
 
@@ -221,21 +238,26 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
 
 
 template <int NDIM>
-__global__ __launch_bounds__(NT) void k_advect(AdvectArgs A) {
+__global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
+                                               const float* __restrict__ Vg, const float* __restrict__ stg,
+                                               float* __restrict__ stog, AdvectArgs A) {
   __shared__ float sh[NT / 64];
   const int tix = xcd_tile(gridDim.x);
-  const Tile t = A.tl[tix];
-  const PairDev& P = A.pd[t.pair];
+  const Tile t = tl[tix];
+  const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int N = (int)P.N;
   const int sxy = nx * ny;
   const float dt = P.dt, rdt = P.rho * P.dt;
-  const float* V = A.V + NDIM * P.off;
-  const float* I = A.st + 2 * P.off;
-  const float* Z = I + N;
-  float* Io = A.st_out ? A.st_out + 2 * P.off : nullptr;
+  const float* __restrict__ V = Vg + NDIM * P.off;
+  const float* __restrict__ I = stg + 2 * P.off;
+  const float* __restrict__ Z = I + N;
+  float* __restrict__ Io = stog ? stog + 2 * P.off : nullptr;
   float reg = 0.f, ssd = 0.f, dm = 0.f;
-  for (int j = threadIdx.x; j < t.b; j += NT) {
+#pragma unroll
+  for (int k = 0; k < ELEM / NT; ++k) {
+    const int j = threadIdx.x + k * NT;
+    if (j >= t.b) continue;
     const int idx = t.a + j;
     const int xq = idx % nx;
     const int yq = (idx / nx) % ny;
@@ -321,137 +343,234 @@ __global__ __launch_bounds__(NT) void k_advect(AdvectArgs A) {
 }
 
 // ----------------------------------------------------------------------------
-// adjoint of the advection (global-atomic scatter)
+// adjoint of the advection, tile-owned, gather form
 // ----------------------------------------------------------------------------
 //
 // For each arrival point q with cotangents (Ib, zb) of (I_{t+1}, z_{t+1}):
 //   zh_bar = rho dt Ib + (1 - dt div v) zb,   div_bar = -dt zh zb,
-//   Ibar_t += Interp^T(Ib),  zbar_t += Interp^T(zh_bar)       (scatter-add)
-//   vbar_c = -dt (Ib dInterp(I_t)/dy_c + zh_bar dInterp(z_t)/dy_c)
-// div_bar is stored; k_divT then adds D_c^T div_bar to vbar_c.
+//   Ibar_t += Interp^T(Ib),  zbar_t += Interp^T(zh_bar)
+//   vbar_c = -dt (Ib dInterp(I_t)/dy_c + zh_bar dInterp(z_t)/dy_c) + D_c^T div_bar
+//
+// A block owns a tile P of outputs. With D = max |dt v| of this pair and step
+// (recorded by the forward pass) every corner a foot touches lies within
+// H = floor(D) + 1 cells of its arrival point, so only the q in P +- H reach
+// P. Phase 1 visits those q and leaves one record per q in LDS (cell of the
+// foot, its fractions, Ib and zh_bar), plus div_bar on P +- 1 and the
+// foot-point part of vbar on P. Phase 2 forms Interp^T at each p of P as a
+// gather over the (2H+1)^d candidate q around it, in a fixed order: no
+// atomics, deterministic, each output written once. For D >= HS (or when
+// forced) the block instead scatters its own q with global atomics into the
+// accumulator, which the previous adjoint step (or the last forward step)
+// cleared.
+__device__ __forceinline__ float diffT_lds(const float* g, int b, int j, int n, int s) {
+  if (j == 0) return -0.5f * (g[b] + g[b + s]);
+  if (j == n - 1) return 0.5f * (g[b - s] + g[b]);
+  return 0.5f * (g[b - s] - g[b + s]);
+}
 
+// Phase-1 work for one arrival point q (local coordinates l* relative to P):
+// its record, div_bar (on P +- 1), the global scatter (fallback mode) and,
+// for q in P, the foot-point part of vbar (returned in vq).
 template <int NDIM>
-__global__ __launch_bounds__(NT) void k_adv_adj(AdjArgs A) {
-  const Tile t = A.tl[xcd_tile(gridDim.x)];
-  const PairDev& P = A.pd[t.pair];
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int N = (int)P.N;
+__device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool inP, bool gmode, int x0, int y0,
+                                          int z0, int nx, int ny, int nz, int N, float dt, float rdt,
+                                          const float* __restrict__ V, const float* __restrict__ I,
+                                          const float* __restrict__ Z, const float* __restrict__ AB,
+                                          float* __restrict__ SI, float* __restrict__ SZ, int* rcell,
+                                          float (*rf)[ADJ_NQ<NDIM>()], float* rib, float* rzb, float* dbar,
+                                          float vq[NDIM]) {
+  constexpr int PX = NDIM == 2 ? ADJ2_X : ADJ3_X;
+  constexpr int PY = NDIM == 2 ? ADJ2_Y : ADJ3_Y;
+  constexpr int PZ = NDIM == 2 ? 1 : ADJ3_Z;
+  constexpr int HS = NDIM == 2 ? ADJ2_HS : ADJ3_HS;
+  constexpr int DX = PX + 2, DY = PY + 2;
+  constexpr int ZO = NDIM == 3 ? 1 : 0;
+  constexpr int NC = NDIM == 3 ? 8 : 4;
+  constexpr int COFF = 2 * HS;
   const int sxy = nx * ny;
-  const float dt = P.dt, rdt = P.rho * P.dt;
-  const float* V = A.V + NDIM * P.off;
-  const float* I = A.st + 2 * P.off;
-  const float* Z = I + N;
-  const float* AB = A.ab_in + 2 * P.off;
-  float* SI = A.sc + 2 * P.off;
-  float* SZ = SI + N;
-  float* DB = A.db + P.off;
-  float* VB = A.vb + NDIM * P.off;
-  for (int j = threadIdx.x; j < t.b; j += NT) {
-    const int idx = t.a + j;
-    const int xq = idx % nx;
-    const int yq = (idx / nx) % ny;
-    const int zq = idx / sxy;
-    float div = 0.5f * (V[(NDIM - 1) * N + idx + up(xq, nx, 1)] - V[(NDIM - 1) * N + idx - dn(xq, 1)]);
-    div += 0.5f * (V[(NDIM - 2) * N + idx + up(yq, ny, nx)] - V[(NDIM - 2) * N + idx - dn(yq, nx)]);
-    if (NDIM == 3) div += 0.5f * (V[idx + up(zq, nz, sxy)] - V[idx - dn(zq, sxy)]);
-    const Axis ax = foot_axis(xq, -dt * V[(NDIM - 1) * N + idx], nx);
-    const Axis ay = foot_axis(yq, -dt * V[(NDIM - 2) * N + idx], ny);
-    const float Ib = AB[idx];
-    const float zb = AB[N + idx];
-    const float wx0 = 1.f - ax.f, wx1 = ax.f, wy0 = 1.f - ay.f, wy1 = ay.f;
-    if (NDIM == 2) {
-      const int c00 = ay.i * nx + ax.i, c10 = c00 + nx;
-      const float i00 = I[c00], i01 = I[c00 + 1], i10 = I[c10], i11 = I[c10 + 1];
-      const float z00 = Z[c00], z01 = Z[c00 + 1], z10 = Z[c10], z11 = Z[c10 + 1];
-      const float zh = wy0 * (wx0 * z00 + wx1 * z01) + wy1 * (wx0 * z10 + wx1 * z11);
-      const float zhb = fmaf(rdt, Ib, (1.f - dt * div) * zb);
-      DB[idx] = -dt * zh * zb;
-      const float w00 = wy0 * wx0, w01 = wy0 * wx1, w10 = wy1 * wx0, w11 = wy1 * wx1;
-      unsafeAtomicAdd(SI + c00, w00 * Ib);
-      unsafeAtomicAdd(SI + c00 + 1, w01 * Ib);
-      unsafeAtomicAdd(SI + c10, w10 * Ib);
-      unsafeAtomicAdd(SI + c10 + 1, w11 * Ib);
-      unsafeAtomicAdd(SZ + c00, w00 * zhb);
-      unsafeAtomicAdd(SZ + c00 + 1, w01 * zhb);
-      unsafeAtomicAdd(SZ + c10, w10 * zhb);
-      unsafeAtomicAdd(SZ + c10 + 1, w11 * zhb);
-      const float gIy = ay.live * (wx0 * (i10 - i00) + wx1 * (i11 - i01));
-      const float gIx = ax.live * (wy0 * (i01 - i00) + wy1 * (i11 - i10));
-      const float gzy = ay.live * (wx0 * (z10 - z00) + wx1 * (z11 - z01));
-      const float gzx = ax.live * (wy0 * (z01 - z00) + wy1 * (z11 - z10));
-      VB[idx] = -dt * fmaf(Ib, gIy, zhb * gzy);
-      VB[N + idx] = -dt * fmaf(Ib, gIx, zhb * gzx);
-    } else {
-      const Axis az = foot_axis(zq, -dt * V[idx], nz);
-      const float wz0 = 1.f - az.f, wz1 = az.f;
-      const int c000 = az.i * sxy + ay.i * nx + ax.i;
-      const int cc[8] = {c000, c000 + 1, c000 + nx, c000 + nx + 1,
-                         c000 + sxy, c000 + sxy + 1, c000 + sxy + nx, c000 + sxy + nx + 1};
-      float iv[8], zv[8];
+  const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
+  const bool inP1 = lx >= -1 && lx <= PX && ly >= -1 && ly <= PY && (NDIM == 2 || (lz >= -1 && lz <= PZ));
+  const int idx = (qz * ny + qy) * nx + qx;
+  float div = 0.5f * (V[(NDIM - 1) * N + idx + up(qx, nx, 1)] - V[(NDIM - 1) * N + idx - dn(qx, 1)]);
+  div += 0.5f * (V[(NDIM - 2) * N + idx + up(qy, ny, nx)] - V[(NDIM - 2) * N + idx - dn(qy, nx)]);
+  if (NDIM == 3) div += 0.5f * (V[idx + up(qz, nz, sxy)] - V[idx - dn(qz, sxy)]);
+  const float Ib = AB[idx];
+  const float zb = AB[N + idx];
+  const Axis ax = foot_axis(qx, -dt * V[(NDIM - 1) * N + idx], nx);
+  const Axis ay = foot_axis(qy, -dt * V[(NDIM - 2) * N + idx], ny);
+  Axis az;
+  if (NDIM == 3) {
+    az = foot_axis(qz, -dt * V[idx], nz);
+  } else {
+    az.i = 0; az.f = 0.f; az.live = 0.f;
+  }
+  const float wz[2] = {1.f - az.f, az.f}, wy[2] = {1.f - ay.f, ay.f}, wx[2] = {1.f - ax.f, ax.f};
+  const int c0 = az.i * sxy + ay.i * nx + ax.i;
+  float zv[NC], iv[NC];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) { iv[k] = I[cc[k]]; zv[k] = Z[cc[k]]; }
-      // corner k = 4 bz + 2 by + bx
-      const float wz[2] = {wz0, wz1}, wy[2] = {wy0, wy1}, wx[2] = {wx0, wx1};
-      float zh = 0.f;
-      float w[8];
+  for (int k = 0; k < NC; ++k) {
+    const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
+    const int g = c0 + bz * sxy + by * nx + bx;
+    zv[k] = Z[g];
+    iv[k] = inP ? I[g] : 0.f;
+  }
+  float zh = 0.f;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        w[k] = wz[k >> 2] * wy[(k >> 1) & 1] * wx[k & 1];
-        zh = fmaf(w[k], zv[k], zh);
-      }
-      const float zhb = fmaf(rdt, Ib, (1.f - dt * div) * zb);
-      DB[idx] = -dt * zh * zb;
+  for (int k = 0; k < NC; ++k) {
+    const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
+    zh = fmaf((NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx], zv[k], zh);
+  }
+  const float zhb = fmaf(rdt, Ib, (1.f - dt * div) * zb);
+  if (inP1) dbar[((lz + ZO) * DY + (ly + 1)) * DX + (lx + 1)] = -dt * zh * zb;
+  if (gmode) {
+    rcell[li] = (ax.i - x0 + COFF) | ((ay.i - y0 + COFF) << 8) | ((NDIM == 3 ? az.i - z0 + COFF : 0) << 16);
+    rf[NDIM - 1][li] = ax.f;
+    rf[NDIM - 2][li] = ay.f;
+    if (NDIM == 3) rf[0][li] = az.f;
+    rib[li] = Ib;
+    rzb[li] = zhb;
+  } else {
+    rcell[li] = -1;
+    if (inP) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        unsafeAtomicAdd(SI + cc[k], w[k] * Ib);
-        unsafeAtomicAdd(SZ + cc[k], w[k] * zhb);
-      }
-      // derivatives of the trilinear weights along each axis
-      float gI[3] = {0.f, 0.f, 0.f}, gZ[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < NC; ++k) {
         const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-        const float dz = (bz ? 1.f : -1.f) * wy[by] * wx[bx];
-        const float dy = (by ? 1.f : -1.f) * wz[bz] * wx[bx];
-        const float dxw = (bx ? 1.f : -1.f) * wz[bz] * wy[by];
-        gI[0] = fmaf(dz, iv[k], gI[0]); gZ[0] = fmaf(dz, zv[k], gZ[0]);
-        gI[1] = fmaf(dy, iv[k], gI[1]); gZ[1] = fmaf(dy, zv[k], gZ[1]);
-        gI[2] = fmaf(dxw, iv[k], gI[2]); gZ[2] = fmaf(dxw, zv[k], gZ[2]);
+        const float w = (NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx];
+        const int g = c0 + bz * sxy + by * nx + bx;
+        unsafeAtomicAdd(SI + g, w * Ib);
+        unsafeAtomicAdd(SZ + g, w * zhb);
       }
-      const float live[3] = {az.live, ay.live, ax.live};
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        VB[c * N + idx] = -dt * live[c] * fmaf(Ib, gI[c], zhb * gZ[c]);
     }
+  }
+  if (inP) {
+    float gI[3] = {0.f, 0.f, 0.f}, gZ[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
+      const float wzz = NDIM == 3 ? wz[bz] : 1.f;
+      const float ddz = (bz ? 1.f : -1.f) * wy[by] * wx[bx];
+      const float ddy = (by ? 1.f : -1.f) * wzz * wx[bx];
+      const float ddx = (bx ? 1.f : -1.f) * wzz * wy[by];
+      gI[0] = fmaf(ddz, iv[k], gI[0]); gZ[0] = fmaf(ddz, zv[k], gZ[0]);
+      gI[1] = fmaf(ddy, iv[k], gI[1]); gZ[1] = fmaf(ddy, zv[k], gZ[1]);
+      gI[2] = fmaf(ddx, iv[k], gI[2]); gZ[2] = fmaf(ddx, zv[k], gZ[2]);
+    }
+    vq[NDIM - 1] = -dt * ax.live * fmaf(Ib, gI[2], zhb * gZ[2]);
+    vq[NDIM - 2] = -dt * ay.live * fmaf(Ib, gI[1], zhb * gZ[1]);
+    if (NDIM == 3) vq[0] = -dt * az.live * fmaf(Ib, gI[0], zhb * gZ[0]);
   }
 }
 
-// vbar_c += D_c^T div_bar (transpose of the clamped central difference:
-// interior (g[j-1] - g[j+1]) / 2, first -(g[0] + g[1]) / 2, last
-// (g[n-2] + g[n-1]) / 2).
-__device__ __forceinline__ float diffT(const float* g, int idx, int j, int n, int s) {
-  if (j == 0) return -0.5f * (g[idx] + g[idx + s]);
-  if (j == n - 1) return 0.5f * (g[idx - s] + g[idx]);
-  return 0.5f * (g[idx - s] - g[idx + s]);
-}
-
 template <int NDIM>
-__global__ __launch_bounds__(NT) void k_divT(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
-                                             const float* __restrict__ db, float* __restrict__ vb) {
-  const Tile t = tl[xcd_tile(gridDim.x)];
-  const PairDev& P = pd[t.pair];
+__global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__ pd, const Tile* __restrict__ tla,
+                                                     const float* __restrict__ Vg, const float* __restrict__ stg,
+                                                     const float* __restrict__ abg, float* __restrict__ scg,
+                                                     float* __restrict__ vbg, AdjArgs A) {
+  constexpr int PX = NDIM == 2 ? ADJ2_X : ADJ3_X;
+  constexpr int PY = NDIM == 2 ? ADJ2_Y : ADJ3_Y;
+  constexpr int PZ = NDIM == 2 ? 1 : ADJ3_Z;
+  constexpr int HS = NDIM == 2 ? ADJ2_HS : ADJ3_HS;   // gather mode handles D < HS
+  constexpr int NP = PX * PY * PZ;
+  constexpr int PPT = NP / NT;                        // outputs per thread
+  static_assert(NP % NT == 0, "tile must be a multiple of the block");
+  // P +- 1 (div_bar) and P +- HS (arrival points that may reach P)
+  constexpr int DX = PX + 2, DY = PY + 2, DZ = NDIM == 3 ? PZ + 2 : 1;
+  constexpr int QX = PX + 2 * HS, QY = PY + 2 * HS;
+  constexpr int NQ = ADJ_NQ<NDIM>();
+  constexpr int ZO = NDIM == 3 ? 1 : 0;
+  constexpr int ZH = NDIM == 3 ? HS : 0;
+  constexpr int COFF = 2 * HS;  // cell coordinates relative to P, shifted to be >= 0
+  __shared__ int rcell[NQ];
+  __shared__ float rf[NDIM][NQ];
+  __shared__ float rib[NQ], rzb[NQ];
+  __shared__ float dbar[DX * DY * DZ];
+  const Tile tl = tla[xcd_tile(gridDim.x)];
+  const PairDev& P = pd[tl.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int N = (int)P.N;
-  const int sxy = nx * ny;
-  const float* DB = db + P.off;
-  float* VB = vb + NDIM * P.off;
-  for (int j = threadIdx.x; j < t.b; j += NT) {
-    const int idx = t.a + j;
-    const int xq = idx % nx;
-    const int yq = (idx / nx) % ny;
-    VB[(NDIM - 1) * N + idx] += diffT(DB, idx, xq, nx, 1);
-    VB[(NDIM - 2) * N + idx] += diffT(DB, idx, yq, ny, nx);
-    if (NDIM == 3) VB[idx] += diffT(DB, idx, idx / sxy, nz, sxy);
+  const float dt = P.dt, rdt = P.rho * P.dt;
+  const int x0 = tl.a, y0 = tl.b, z0 = tl.c;
+  const float D = __uint_as_float(A.dmax[(long long)tl.pair * A.T + A.t]);
+  const bool gmode = !A.force_global && (D < (float)HS);
+  const int H = gmode ? (int)floorf(D) + 1 : 1;
+  const float* __restrict__ V = Vg + NDIM * P.off;
+  const float* __restrict__ I = stg + 2 * P.off;
+  const float* __restrict__ Z = I + N;
+  const float* __restrict__ AB = abg + 2 * P.off;
+  float* __restrict__ SI = scg + 2 * P.off;
+  float* __restrict__ SZ = SI + N;
+  float* __restrict__ VB = vbg + NDIM * P.off;
+
+  // phase 1a: the outputs of this thread (same mapping as phase 2)
+  float vq[PPT][NDIM];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = threadIdx.x + k * NT;
+    const int lx = li % PX, ly = (li / PX) % PY, lz = li / (PX * PY);
+    const int r = ((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS);
+#pragma unroll
+    for (int c = 0; c < NDIM; ++c) vq[k][c] = 0.f;
+    if (x0 + lx < nx && y0 + ly < ny && z0 + lz < nz)
+      adj_point<NDIM>(lx, ly, lz, r, true, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ,
+                      rcell, rf, rib, rzb, dbar, vq[k]);
+    else
+      rcell[r] = -1;
+  }
+  // phase 1b: the halo points P +- H around P (records and div_bar only)
+  const int hq = gmode ? H : 1;
+#pragma unroll 2
+  for (int li = threadIdx.x; li < NQ; li += NT) {
+    const int lx = li % QX - HS, ly = (li / QX) % QY - HS, lz = NDIM == 3 ? li / (QX * QY) - HS : 0;
+    const bool inP = lx >= 0 && lx < PX && ly >= 0 && ly < PY && lz >= 0 && lz < PZ;
+    if (inP) continue;
+    const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
+    const bool visit = lx >= -hq && lx < PX + hq && ly >= -hq && ly < PY + hq &&
+                       (NDIM == 2 || (lz >= -hq && lz < PZ + hq)) && qx >= 0 && qx < nx && qy >= 0 &&
+                       qy < ny && qz >= 0 && qz < nz;
+    if (!visit) {
+      rcell[li] = -1;
+      continue;
+    }
+    float dummy[NDIM];
+    adj_point<NDIM>(lx, ly, lz, li, false, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ,
+                    rcell, rf, rib, rzb, dbar, dummy);
+  }
+  __syncthreads();
+
+  // phase 2: vbar and the gathered transpose of the interpolation
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = threadIdx.x + k * NT;
+    const int lx = li % PX, ly = (li / PX) % PY, lz = li / (PX * PY);
+    const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
+    if (qx >= nx || qy >= ny || (NDIM == 3 && qz >= nz)) continue;
+    const int idx = (qz * ny + qy) * nx + qx;
+    const int b = ((lz + ZO) * DY + (ly + 1)) * DX + (lx + 1);
+    VB[(NDIM - 1) * N + idx] = vq[k][NDIM - 1] + diffT_lds(dbar, b, qx, nx, 1);
+    VB[(NDIM - 2) * N + idx] = vq[k][NDIM - 2] + diffT_lds(dbar, b, qy, ny, DX);
+    if (NDIM == 3) VB[idx] = vq[k][0] + diffT_lds(dbar, b, qz, nz, DX * DY);
+    if (gmode) {
+      // Interp^T at p: sum over candidate arrival points q = p + (oz, oy, ox)
+      float accI = 0.f, accZ = 0.f;
+      const int hz = NDIM == 3 ? H : 0;
+      for (int oz = -hz; oz <= hz; ++oz)
+        for (int oy = -H; oy <= H; ++oy)
+          for (int ox = -H; ox <= H; ++ox) {
+            const int r = ((lz + oz + ZH) * QY + (ly + oy + HS)) * QX + (lx + ox + HS);
+            const int code = rcell[r];
+            if (code < 0) continue;
+            const int bx = lx + COFF - (code & 0xff);
+            const int by = ly + COFF - ((code >> 8) & 0xff);
+            const int bz = NDIM == 3 ? lz + COFF - ((code >> 16) & 0xff) : 0;
+            if ((unsigned)bx > 1u || (unsigned)by > 1u || (unsigned)bz > 1u) continue;
+            float w = (bx ? rf[NDIM - 1][r] : 1.f - rf[NDIM - 1][r]) * (by ? rf[NDIM - 2][r] : 1.f - rf[NDIM - 2][r]);
+            if (NDIM == 3) w *= bz ? rf[0][r] : 1.f - rf[0][r];
+            accI = fmaf(w, rib[r], accI);
+            accZ = fmaf(w, rzb[r], accZ);
+          }
+      SI[idx] = accI;
+      SZ[idx] = accZ;
+    }
   }
 }
 
@@ -460,21 +579,32 @@ __global__ __launch_bounds__(NT) void k_divT(const PairDev* __restrict__ pd, con
 //   zbar_t = scatter part + sum_c mbar_c D_c I_t
 //   Ibar_t = scatter part + sum_c D_c^T (z_t mbar_c)
 // At t = 0 only dH/dp0 = zbar_0 + 2 lambda rho p0 is written. The scatter
-// accumulator is cleared for the next (earlier) step.
+// accumulator is cleared when the next (earlier) step scatters with global
+// atomics.
 
 template <int NDIM>
-__global__ __launch_bounds__(NT) void k_epilogue(EpiArgs A) {
-  const Tile t = A.tl[xcd_tile(gridDim.x)];
-  const PairDev& P = A.pd[t.pair];
+__global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
+                                                 const float* __restrict__ mbg, const float* __restrict__ stg,
+                                                 float* __restrict__ scg, float* __restrict__ abg, EpiArgs A) {
+  const Tile t = tl[xcd_tile(gridDim.x)];
+  const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int N = (int)P.N;
   const int sxy = nx * ny;
-  const float* MB = A.mb + NDIM * P.off;
-  const float* I = A.st + 2 * P.off;
-  const float* Z = I + N;
-  float* SI = A.sc + 2 * P.off;
-  float* SZ = SI + N;
-  for (int j = threadIdx.x; j < t.b; j += NT) {
+  const float* __restrict__ MB = mbg + NDIM * P.off;
+  const float* __restrict__ I = stg + 2 * P.off;
+  const float* __restrict__ Z = I + N;
+  float* __restrict__ SI = scg + 2 * P.off;
+  float* __restrict__ SZ = SI + N;
+  bool clear = false;
+  if (!A.first) {
+    const float Dn = __uint_as_float(A.dmax[(long long)t.pair * A.T + A.t - 1]);
+    clear = A.force_global || !(Dn < (float)(NDIM == 2 ? ADJ2_HS : ADJ3_HS));
+  }
+#pragma unroll
+  for (int k = 0; k < ELEM / NT; ++k) {
+    const int j = threadIdx.x + k * NT;
+    if (j >= t.b) continue;
     const int idx = t.a + j;
     const int xq = idx % nx;
     const int yq = (idx / nx) % ny;
@@ -505,12 +635,14 @@ __global__ __launch_bounds__(NT) void k_epilogue(EpiArgs A) {
     if (A.first) {
       if (P.outG) P.outG[idx] = fmaf(2.f * P.lam * P.rho, Z[idx], zbar);
     } else {
-      float* AB = A.ab_out + 2 * P.off;
+      float* __restrict__ AB = abg + 2 * P.off;
       AB[idx] = Ibar;
       AB[N + idx] = zbar;
     }
-    SI[idx] = 0.f;
-    SZ[idx] = 0.f;
+    if (clear) {
+      SI[idx] = 0.f;
+      SZ[idx] = 0.f;
+    }
   }
 }
 
@@ -568,9 +700,10 @@ hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* t
 template <int NDIM, bool PASSZ>
 static void spass_dispatch(int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds, const float* src,
                            float* dst, const float* extra, hipStream_t s) {
-  if (mode == 0) k_spass<NDIM, PASSZ, 0><<<nt, NT, lds, s>>>(pd, tl, src, dst, extra);
-  else if (mode == 1) k_spass<NDIM, PASSZ, 1><<<nt, NT, lds, s>>>(pd, tl, src, dst, extra);
-  else k_spass<NDIM, PASSZ, 2><<<nt, NT, lds, s>>>(pd, tl, src, dst, extra);
+  const dim3 grid(nt, NDIM);
+  if (mode == 0) k_spass<NDIM, PASSZ, 0><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
+  else if (mode == 1) k_spass<NDIM, PASSZ, 1><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
+  else k_spass<NDIM, PASSZ, 2><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
 }
 
 hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds,
@@ -582,27 +715,20 @@ hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const
 }
 
 hipError_t launch_advect(int ndim, int nt, const AdvectArgs& a, hipStream_t s) {
-  if (ndim == 2) k_advect<2><<<nt, NT, 0, s>>>(a);
-  else k_advect<3><<<nt, NT, 0, s>>>(a);
+  if (ndim == 2) k_advect<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+  else k_advect<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
   return post();
 }
 
 hipError_t launch_adv_adj(int ndim, int nt, const AdjArgs& a, hipStream_t s) {
-  if (ndim == 2) k_adv_adj<2><<<nt, NT, 0, s>>>(a);
-  else k_adv_adj<3><<<nt, NT, 0, s>>>(a);
-  return post();
-}
-
-hipError_t launch_divT(int ndim, const PairDev* pd, const Tile* tl, int nt, const float* db, float* vb,
-                       hipStream_t s) {
-  if (ndim == 2) k_divT<2><<<nt, NT, 0, s>>>(pd, tl, db, vb);
-  else k_divT<3><<<nt, NT, 0, s>>>(pd, tl, db, vb);
+  if (ndim == 2) k_adv_adj_tile<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+  else k_adv_adj_tile<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
   return post();
 }
 
 hipError_t launch_epilogue(int ndim, int nt, const EpiArgs& a, hipStream_t s) {
-  if (ndim == 2) k_epilogue<2><<<nt, NT, 0, s>>>(a);
-  else k_epilogue<3><<<nt, NT, 0, s>>>(a);
+  if (ndim == 2) k_epilogue<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+  else k_epilogue<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
   return post();
 }
 

@@ -46,27 +46,27 @@ enum Op { OP_FORWARD = 0, OP_COST = 1, OP_GRAD = 2 };
 struct Wave {
   std::vector<int> ids;
   std::vector<PairDev> pdev;
-  std::vector<Tile> te, tx, ty, tz;
+  std::vector<Tile> te, tx, ty, tz, ta;
   long long ntot = 0;                // padded voxel total
   size_t lds_x = 0, lds_y = 0, lds_z = 0;
   // header offsets (bytes from the workspace base)
-  size_t o_pd = 0, o_te = 0, o_tx = 0, o_ty = 0, o_tz = 0, o_dmax = 0, o_rreg = 0, o_rssd = 0;
+  size_t o_pd = 0, o_te = 0, o_tx = 0, o_ty = 0, o_tz = 0, o_ta = 0, o_dmax = 0, o_rreg = 0, o_rssd = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
 };
 
 struct Fields {  // byte offsets of the field arrays inside the field region
-  size_t st, vs, u, u2, ab, sc, vb, db, end;
+  size_t st, vs, u, u2, ab, sc, vb, end;
 };
 
 // Kernel families, for the profiling statistics.
 enum KId {
   KI_FILL, KI_INIT, KI_XPASS_M, KI_XPASS_V, KI_SPASS_MID, KI_SPASS_V, KI_SPASS_MBAR,
-  KI_ADVECT, KI_ADV_ADJ, KI_DIVT, KI_EPILOGUE, KI_FINALIZE, KI_COUNT
+  KI_ADVECT, KI_ADV_ADJ, KI_EPILOGUE, KI_FINALIZE, KI_COUNT
 };
 const char* const KNAMES[KI_COUNT] = {
     "fill", "init", "xpass_gradmul", "xpass_plain", "spass_mid", "spass_v", "spass_mbar",
-    "advect", "advect_adjoint", "divT", "epilogue", "finalize"};
+    "advect", "advect_adjoint", "epilogue", "finalize"};
 
 // Event pairs around launches; resolved after the stream is synchronised.
 struct Prof {
@@ -156,7 +156,6 @@ Fields field_layout(const shoot_plan_s* p, long long ntot) {
   F.ab = o; o = align_up(o + 2 * 2 * ntot * f, ALIGN);
   F.sc = o; o = align_up(o + 2 * ntot * f, ALIGN);
   F.vb = o; o = align_up(o + d * ntot * f, ALIGN);
-  F.db = o; o = align_up(o + ntot * f, ALIGN);
   F.end = o;
   return F;
 }
@@ -214,7 +213,7 @@ shoot_status validate(const shoot_pair* pairs, int32_t n, int32_t T) {
 
 // Builds descriptors and tile lists of one wave (header offsets are set later).
 void build_wave(shoot_plan_s* p, Wave& w) {
-  w.pdev.clear(); w.te.clear(); w.tx.clear(); w.ty.clear(); w.tz.clear();
+  w.pdev.clear(); w.te.clear(); w.tx.clear(); w.ty.clear(); w.tz.clear(); w.ta.clear();
   long long off = 0;
   w.lds_x = w.lds_y = w.lds_z = 0;
   for (size_t li = 0; li < w.ids.size(); ++li) {
@@ -266,6 +265,14 @@ void build_wave(shoot_plan_s* p, Wave& w) {
           for (int s0 = 0; s0 < P.nz; s0 += SSEG) w.tz.push_back(Tile{pi, x0, o, s0});
       w.lds_z = std::max(w.lds_z, sb);
     }
+    // adjoint tiles
+    {
+      const int AX = p->ndim == 2 ? ADJ2_X : ADJ3_X, AY = p->ndim == 2 ? ADJ2_Y : ADJ3_Y;
+      const int AZ = p->ndim == 2 ? 1 : ADJ3_Z;
+      for (int z0 = 0; z0 < P.nz; z0 += AZ)
+        for (int y0 = 0; y0 < P.ny; y0 += AY)
+          for (int x0 = 0; x0 < P.nx; x0 += AX) w.ta.push_back(Tile{pi, x0, y0, z0});
+    }
     w.pdev.push_back(P);
   }
   w.ntot = off;
@@ -280,6 +287,7 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   w.o_tx = take(w.tx.size() * sizeof(Tile));
   w.o_ty = take(w.ty.size() * sizeof(Tile));
   w.o_tz = take(w.tz.size() * sizeof(Tile));
+  w.o_ta = take(w.ta.size() * sizeof(Tile));
   w.o_dmax = take(w.pdev.size() * (size_t)p->T * sizeof(unsigned));
   w.o_rreg = take(w.te.size() * sizeof(float));
   w.o_rssd = take(w.te.size() * sizeof(float));
@@ -294,11 +302,11 @@ struct Ctx {
   Wave* w;
   hipStream_t s;
   const PairDev* pd;
-  const Tile *te, *tx, *ty, *tz;
-  int nte, ntx, nty, ntz;
+  const Tile *te, *tx, *ty, *tz, *ta;
+  int nte, ntx, nty, ntz, nta;
   unsigned* dmax;
   float *rreg, *rssd;
-  float *st, *vs, *u, *u2, *ab, *sc, *vb, *db;
+  float *st, *vs, *u, *u2, *ab, *sc, *vb;
   long long ntot;
   Prof* prof;
 };
@@ -312,13 +320,14 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   c.tx = (const Tile*)(b + w.o_tx); c.ntx = (int)w.tx.size();
   c.ty = (const Tile*)(b + w.o_ty); c.nty = (int)w.ty.size();
   c.tz = (const Tile*)(b + w.o_tz); c.ntz = (int)w.tz.size();
+  c.ta = (const Tile*)(b + w.o_ta); c.nta = (int)w.ta.size();
   c.dmax = (unsigned*)(b + w.o_dmax);
   c.rreg = (float*)(b + w.o_rreg);
   c.rssd = (float*)(b + w.o_rssd);
   char* f = b + p->header_total;
   const Fields F = field_layout(p, w.ntot);
   c.st = (float*)(f + F.st); c.vs = (float*)(f + F.vs); c.u = (float*)(f + F.u); c.u2 = (float*)(f + F.u2);
-  c.ab = (float*)(f + F.ab); c.sc = (float*)(f + F.sc); c.vb = (float*)(f + F.vb); c.db = (float*)(f + F.db);
+  c.ab = (float*)(f + F.ab); c.sc = (float*)(f + F.sc); c.vb = (float*)(f + F.vb);
   c.ntot = w.ntot;
   return c;
 }
@@ -385,11 +394,12 @@ hipError_t run_forward(const Ctx& c, int op) {
 // Adjoint of step t: (Ibar_{t+1}, zbar_{t+1}) in AB(t+1) -> AB(t) (or dH/dp0 at t = 0).
 hipError_t bwd_step(const Ctx& c, int t) {
   const int nd = c.p->ndim;
+  const int force = (c.p->flags & SHOOT_FORCE_GLOBAL_SCATTER) ? 1 : 0;
   AdjArgs a{};
-  a.pd = c.pd; a.tl = c.te; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
-  a.sc = c.sc; a.db = c.db; a.vb = c.vb;
-  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.nte, a, c.s));
-  LAUNCH(KI_DIVT, launch_divT(nd, c.pd, c.te, c.nte, c.db, c.vb, c.s));
+  a.pd = c.pd; a.tl = c.ta; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
+  a.sc = c.sc; a.vb = c.vb;
+  a.dmax = c.dmax; a.T = c.p->T; a.t = t; a.force_global = force;
+  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.nta, a, c.s));
   // mbar = -G vbar (+ -2 lambda v_0 at t = 0), written back into vb
   LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.w->lds_x, c.vb, c.u, c.s));
   const float* extra = t == 0 ? VS(c, 0) : nullptr;
@@ -402,6 +412,7 @@ hipError_t bwd_step(const Ctx& c, int t) {
   EpiArgs ep{};
   ep.pd = c.pd; ep.tl = c.te; ep.mb = c.vb; ep.st = ST(c, t); ep.sc = c.sc;
   ep.ab_out = t > 0 ? AB(c, t) : nullptr;
+  ep.dmax = c.dmax; ep.T = c.p->T; ep.t = t; ep.force_global = force;
   ep.first = t == 0 ? 1 : 0;
   LAUNCH(KI_EPILOGUE, launch_epilogue(nd, c.nte, ep, c.s));
   return hipSuccess;
@@ -587,6 +598,7 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     put(w.o_tx, w.tx.data(), w.tx.size() * sizeof(Tile));
     put(w.o_ty, w.ty.data(), w.ty.size() * sizeof(Tile));
     put(w.o_tz, w.tz.data(), w.tz.size() * sizeof(Tile));
+    put(w.o_ta, w.ta.data(), w.ta.size() * sizeof(Tile));
   }
   *out = p;
   g_err.clear();

@@ -20,6 +20,17 @@ constexpr int ELEM = 1024;
 // thread produces SRB consecutive outputs along it.
 constexpr int SRB = 16;
 constexpr int SSEG = (NT / 64) * SRB;                  // 64 outputs per tile
+// Adjoint-advection tiles (outputs owned by one block) and the per-step
+// displacement bound (pixels, exclusive) below which a block accumulates in
+// LDS from staged I, z; above it the block falls back to global atomics.
+constexpr int ADJ2_X = 64, ADJ2_Y = 16, ADJ2_HS = 2;
+constexpr int ADJ3_X = 32, ADJ3_Y = 8, ADJ3_Z = 4, ADJ3_HS = 1;
+// arrival points staged per adjoint tile: the tile grown by the bound on each side
+template <int NDIM>
+constexpr int ADJ_NQ() {
+  return NDIM == 2 ? (ADJ2_X + 2 * ADJ2_HS) * (ADJ2_Y + 2 * ADJ2_HS)
+                   : (ADJ3_X + 2 * ADJ3_HS) * (ADJ3_Y + 2 * ADJ3_HS) * (ADJ3_Z + 2 * ADJ3_HS);
+}
 
 // Per-pair descriptor, resident in the workspace. Geometry is stored as
 // (nz, ny, nx) with nz = 1 in 2-D; channel / axis c of a vector field follows
