@@ -8,6 +8,17 @@ namespace shoot {
 // Native 4-float vector: LDS loads of it become one aligned ds_read_b128.
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
+// Global access at element i of a uniform base: the byte offset is formed in
+// 32 bits, so the access uses the scalar-base + 32-bit-offset addressing mode
+// (one VALU op per address instead of a 64-bit add). Every array the kernels
+// index is below 4 GiB per pair.
+__device__ __forceinline__ float gld(const float* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (i << 2));
+}
+__device__ __forceinline__ void gst(float* __restrict__ base, unsigned i, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (i << 2)) = v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

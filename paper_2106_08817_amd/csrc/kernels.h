@@ -47,7 +47,7 @@ struct EpiArgs {
 };
 
 hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s);
-hipError_t launch_init(const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s);
+hipError_t launch_init(int ndim, const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s);
 hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* tl, int nt, size_t lds,
                         const float* src, float* dst, hipStream_t s);
 hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds,

@@ -10,14 +10,40 @@
 //                      z' = zh (1 - dt div v); cost partials at the first and
 //                      last step
 // Adjoint step (transpose of the above, in reverse):
-//   k_adv_adj_tile        tile-owned transpose of the interpolation (LDS
-//                         accumulation), foot-point cotangent and div^T
+//   k_adv_adj_tile     tile-owned transpose of the interpolation (gathered in
+//                      LDS), foot-point cotangent and div^T
 //   k_xpass<plain>, k_spass  G is symmetric, so the same passes smooth vbar
-//   k_epilogue            transpose of m = z D I
+//   k_epilogue         transpose of m = z D I
+//
+// Data movement conventions: loads address a uniform base with an unsigned
+// 32-bit offset, and are issued unconditionally from coordinates clamped into
+// the image (results of out-of-range lanes are discarded), so that the
+// compiler can keep many independent loads in flight.
 #include "kernels.h"
 #include "device_common.h"
 
 namespace shoot {
+
+// Geometry of the block tiles shared by the elementwise kernels.
+template <int NDIM>
+struct Blk {
+  static constexpr int X = NDIM == 2 ? BLK2_X : BLK3_X;
+  static constexpr int Y = NDIM == 2 ? BLK2_Y : BLK3_Y;
+  static constexpr int Z = NDIM == 2 ? 1 : BLK3_Z;
+  static constexpr int HS = NDIM == 2 ? BLK2_HS : BLK3_HS;
+  static constexpr int NP = X * Y * Z;
+  static constexpr int PPT = NP / NT;
+  static_assert(NP % NT == 0, "block tile must be a multiple of the block");
+  // local coordinates of the k-th voxel of thread t (x fastest)
+  __device__ static void local(int t, int k, int& lx, int& ly, int& lz) {
+    const int li = t + k * NT;
+    lx = li % X;
+    ly = (li / X) % Y;
+    lz = li / (X * Y);
+  }
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // ----------------------------------------------------------------------------
 // small utility kernels
@@ -29,16 +55,27 @@ __global__ __launch_bounds__(NT) void k_fill_u32(unsigned* __restrict__ p, long 
 }
 
 // State slot <- (S, p0) for every pair.
+template <int NDIM>
 __global__ __launch_bounds__(NT) void k_init(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                              float* __restrict__ st) {
+  using B = Blk<NDIM>;
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
-  float* I = st + 2 * P.off;
-  float* Z = I + P.N;
-  for (int j = threadIdx.x; j < t.b; j += NT) {
-    const int i = t.a + j;
-    I[i] = P.S[i];
-    Z[i] = P.p0[i];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned N = (unsigned)P.N;
+  float* __restrict__ I = st + 2 * P.off;
+  const float* __restrict__ S = P.S;
+  const float* __restrict__ Q = P.p0;
+#pragma unroll
+  for (int k = 0; k < B::PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    const int x = t.a + lx, y = t.b + ly, z = t.c + lz;
+    if (x < nx && y < ny && z < nz) {
+      const unsigned idx = (unsigned)((z * ny + y) * nx + x);
+      gst(I, idx, gld(S, idx));
+      gst(I, N + idx, gld(Q, idx));
+    }
   }
 }
 
@@ -59,14 +96,14 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz, r = P.r, ntap4 = P.ntap4;
-  const int N = (int)P.N;
+  const unsigned N = (unsigned)P.N;
   const int G4 = (nx + 3) >> 2;
   const int L = 4 * (G4 + ntap4);
   const int row0 = t.a, nrows = t.b;
   const int plane = nrows * L;
 
-  // fill: one wave per row, lanes along the row (every load of a row is
-  // independent, so the unrolled column loop keeps several in flight)
+  // fill: one wave per row, lanes along the row, four columns per lane in
+  // flight (clamped loads, zero outside the row)
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   if (GRADMUL) {
@@ -75,59 +112,82 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
     for (int rl = wv; rl < nrows; rl += NT / 64) {
       const int row = row0 + rl;
       const int y = row % ny;
-      const int rbase = row * nx;
-      const int yu = up(y, ny, nx), yd = dn(y, nx);
-      int zu = 0, zd = 0;
+      const unsigned rbase = (unsigned)(row * nx);
+      const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
+      unsigned zu = 0, zd = 0;
       if (NDIM == 3) {
         const int z = row / ny;
-        zu = up(z, nz, ny * nx);
-        zd = dn(z, ny * nx);
+        zu = (unsigned)up(z, nz, ny * nx);
+        zd = (unsigned)dn(z, ny * nx);
       }
       float* Lrow = lds + rl * L;
-#pragma unroll 4
-      for (int col = lane; col < L; col += 64) {
-        const int x = col - r;
-        float m[NDIM];
+      for (int c0 = 0; c0 < L; c0 += 4 * 64) {
+        float m[4][NDIM];
 #pragma unroll
-        for (int c = 0; c < NDIM; ++c) m[c] = 0.f;
-        if (x >= 0 && x < nx) {
-          const int idx = rbase + x;
-          const float zq = 0.5f * Z[idx];
-          m[NDIM - 1] = zq * (I[idx + up(x, nx, 1)] - I[idx - dn(x, 1)]);
-          m[NDIM - 2] = zq * (I[idx + yu] - I[idx - yd]);
-          if (NDIM == 3) m[0] = zq * (I[idx + zu] - I[idx - zd]);
+        for (int u = 0; u < 4; ++u) {
+          const int x = c0 + u * 64 + lane - r;
+          const int xc = clampi(x, 0, nx - 1);
+          const unsigned idx = rbase + (unsigned)xc;
+          const float zq = 0.5f * gld(Z, idx);
+          const float gx = gld(I, idx + (xc + 1 < nx ? 1u : 0u)) - gld(I, idx - (xc > 0 ? 1u : 0u));
+          const float gy = gld(I, idx + yu) - gld(I, idx - yd);
+          const bool in = x >= 0 && x < nx;
+          m[u][NDIM - 1] = in ? zq * gx : 0.f;
+          m[u][NDIM - 2] = in ? zq * gy : 0.f;
+          if (NDIM == 3) m[u][0] = in ? zq * (gld(I, idx + zu) - gld(I, idx - zd)) : 0.f;
         }
 #pragma unroll
-        for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = m[c];
+        for (int u = 0; u < 4; ++u) {
+          const int col = c0 + u * 64 + lane;
+          if (col < L) {
+#pragma unroll
+            for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = m[u][c];
+          }
+        }
       }
     }
   } else {
     const float* __restrict__ F = src + NDIM * P.off;
     for (int rl = wv; rl < nrows; rl += NT / 64) {
-      const int rbase = (row0 + rl) * nx;
+      const unsigned rbase = (unsigned)((row0 + rl) * nx);
       float* Lrow = lds + rl * L;
-#pragma unroll 4
-      for (int col = lane; col < L; col += 64) {
-        const int x = col - r;
-        const bool in = (x >= 0 && x < nx);
+      for (int c0 = 0; c0 < L; c0 += 4 * 64) {
+        float m[4][NDIM];
 #pragma unroll
-        for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = in ? F[c * N + rbase + x] : 0.f;
+        for (int u = 0; u < 4; ++u) {
+          const int x = c0 + u * 64 + lane - r;
+          const unsigned idx = rbase + (unsigned)clampi(x, 0, nx - 1);
+          const bool in = x >= 0 && x < nx;
+#pragma unroll
+          for (int c = 0; c < NDIM; ++c) {
+            const float v = gld(F, c * N + idx);
+            m[u][c] = in ? v : 0.f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int col = c0 + u * 64 + lane;
+          if (col < L) {
+#pragma unroll
+            for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = m[u][c];
+          }
+        }
       }
     }
   }
   __syncthreads();
 
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
-  float* D = dst + NDIM * P.off;
+  float* __restrict__ D = dst + NDIM * P.off;
   const int ngroups = nrows * G4;
   for (int g = threadIdx.x; g < ngroups; g += NT) {
     const int rl = g / G4;
     const int x = 4 * (g - rl * G4);
-    const int obase = (row0 + rl) * nx + x;
+    const unsigned obase = (unsigned)((row0 + rl) * nx + x);
 #pragma unroll
     for (int c = 0; c < NDIM; ++c) {
-      // row offsets are multiples of four floats: index the LDS as float4 so
-      // the reads are aligned ds_read_b128 (consecutive lanes, consecutive 16 B)
+      // row offsets are multiples of four floats: index the LDS as vf4 so the
+      // reads are aligned ds_read_b128 (consecutive lanes, consecutive 16 B)
       const vf4* R4 = smem4 + ((c * plane + rl * L + x) >> 2);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
       vf4 lo = R4[0];
@@ -162,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
 // staged in LDS as (SSEG + 4 ntap4) rows x 64 floats; LDS row j holds the
 // input at s = s0 - r + j. Each thread produces SRB consecutive outputs.
 // MODE 0: plain pass. MODE 1: negated (v = -G m). MODE 2: negated, plus
-// extra_scale * extra (the regulariser's cotangent at t = 0).
+// -2 lambda * extra (the regulariser's cotangent at t = 0).
 template <int NDIM, bool PASSZ, int MODE>
 __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst,
@@ -172,61 +232,69 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz, r = P.r, ntap4 = P.ntap4;
-  const int N = (int)P.N;
+  const unsigned N = (unsigned)P.N;
   // pass axis: length ns, stride ss; third axis index t.b with stride so
   const int ns = PASSZ ? nz : ny;
-  const int ss = PASSZ ? ny * nx : nx;
-  const int so = PASSZ ? nx : ny * nx;
+  const unsigned ss = (unsigned)(PASSZ ? ny * nx : nx);
+  const unsigned so = (unsigned)(PASSZ ? nx : ny * nx);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int x = t.a + lane;
+  const bool xin = x < nx;
   const int s0 = t.c;
   const int rows = SSEG + 4 * ntap4;
-  const int base = t.b * so + x;           // offset of (s = 0, x) in the pair
-  const float* F = src + NDIM * P.off;
-  float* D = dst + NDIM * P.off;
-  const float* E = (MODE == 2 && extra != nullptr) ? extra + NDIM * P.off : nullptr;
-  const float escale = -2.f * P.lam;
-  const float4* W4 = reinterpret_cast<const float4*>(P.w);
-  const bool xin = x < nx;
+  const int c = blockIdx.y;  // one channel per block
+  const unsigned base = (unsigned)t.b * so + (unsigned)min(x, nx - 1);
+  const float* __restrict__ Fc = src + NDIM * P.off + c * N;
 
-  {
-    const int c = blockIdx.y;  // one channel per block
-    const float* Fc = F + c * N;
-#pragma unroll 8
-    for (int j = wv; j < rows; j += NT / 64) {
-      const int s = s0 - r + j;
-      lds[j * 64 + lane] = (xin && s >= 0 && s < ns) ? Fc[base + s * ss] : 0.f;
+  // fill: clamped loads, eight rows per thread in flight
+  for (int j0 = wv; j0 < rows; j0 += 8 * (NT / 64)) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int s = s0 - r + j0 + u * (NT / 64);
+      const float f = gld(Fc, base + (unsigned)clampi(s, 0, ns - 1) * ss);
+      v[u] = (xin && s >= 0 && s < ns) ? f : 0.f;
     }
-    __syncthreads();
-    float acc[SRB];
 #pragma unroll
-    for (int i = 0; i < SRB; ++i) acc[i] = 0.f;
-    const float* col = lds + (wv * SRB) * 64 + lane;
-    for (int b = 0; b < ntap4; ++b) {
-      const float4 w = W4[b];
-      float win[SRB + 3];
-#pragma unroll
-      for (int j = 0; j < SRB + 3; ++j) win[j] = col[(4 * b + j) * 64];
-#pragma unroll
-      for (int i = 0; i < SRB; ++i) {
-        acc[i] = fmaf(w.x, win[i], acc[i]);
-        acc[i] = fmaf(w.y, win[i + 1], acc[i]);
-        acc[i] = fmaf(w.z, win[i + 2], acc[i]);
-        acc[i] = fmaf(w.w, win[i + 3], acc[i]);
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * (NT / 64);
+      if (j < rows) lds[j * 64 + lane] = v[u];
     }
-    if (xin) {
+  }
+  __syncthreads();
+
+  float acc[SRB];
 #pragma unroll
-      for (int i = 0; i < SRB; ++i) {
-        const int s = s0 + wv * SRB + i;
-        if (s < ns) {
-          const int idx = base + s * ss;
-          float o = acc[i];
-          if (MODE >= 1) o = -o;
-          if (MODE == 2 && E != nullptr) o = fmaf(escale, E[c * N + idx], o);
-          D[c * N + idx] = o;
-        }
+  for (int i = 0; i < SRB; ++i) acc[i] = 0.f;
+  const float4* W4 = reinterpret_cast<const float4*>(P.w);
+  const float* col = lds + (wv * SRB) * 64 + lane;
+  for (int b = 0; b < ntap4; ++b) {
+    const float4 w = W4[b];
+    float win[SRB + 3];
+#pragma unroll
+    for (int j = 0; j < SRB + 3; ++j) win[j] = col[(4 * b + j) * 64];
+#pragma unroll
+    for (int i = 0; i < SRB; ++i) {
+      acc[i] = fmaf(w.x, win[i], acc[i]);
+      acc[i] = fmaf(w.y, win[i + 1], acc[i]);
+      acc[i] = fmaf(w.z, win[i + 2], acc[i]);
+      acc[i] = fmaf(w.w, win[i + 3], acc[i]);
+    }
+  }
+  if (xin) {
+    float* __restrict__ Dc = dst + NDIM * P.off + c * N;
+    const float* __restrict__ Ec = (MODE == 2 && extra != nullptr) ? extra + NDIM * P.off + c * N : nullptr;
+    const float escale = -2.f * P.lam;
+#pragma unroll
+    for (int i = 0; i < SRB; ++i) {
+      const int s = s0 + wv * SRB + i;
+      if (s < ns) {
+        const unsigned idx = base + (unsigned)s * ss;
+        float o = acc[i];
+        if (MODE >= 1) o = -o;
+        if (MODE == 2 && Ec != nullptr) o = fmaf(escale, gld(Ec, idx), o);
+        gst(Dc, idx, o);
       }
     }
   }
@@ -236,18 +304,18 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
 // semi-Lagrangian advection (forward step)
 // ----------------------------------------------------------------------------
 
-
 template <int NDIM>
 __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                const float* __restrict__ Vg, const float* __restrict__ stg,
                                                float* __restrict__ stog, AdvectArgs A) {
+  using B = Blk<NDIM>;
   __shared__ float sh[NT / 64];
   const int tix = xcd_tile(gridDim.x);
   const Tile t = tl[tix];
   const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int N = (int)P.N;
-  const int sxy = nx * ny;
+  const unsigned N = (unsigned)P.N;
+  const unsigned sxy = (unsigned)(nx * ny);
   const float dt = P.dt, rdt = P.rho * P.dt;
   const float* __restrict__ V = Vg + NDIM * P.off;
   const float* __restrict__ I = stg + 2 * P.off;
@@ -255,55 +323,59 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
   float* __restrict__ Io = stog ? stog + 2 * P.off : nullptr;
   float reg = 0.f, ssd = 0.f, dm = 0.f;
 #pragma unroll
-  for (int k = 0; k < ELEM / NT; ++k) {
-    const int j = threadIdx.x + k * NT;
-    if (j >= t.b) continue;
-    const int idx = t.a + j;
-    const int xq = idx % nx;
-    const int yq = (idx / nx) % ny;
-    const int zq = idx / sxy;
+  for (int k = 0; k < B::PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    const bool inside = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
+    const int xq = min(t.a + lx, nx - 1), yq = min(t.b + ly, ny - 1), zq = min(t.c + lz, nz - 1);
+    const unsigned idx = (unsigned)((zq * ny + yq) * nx + xq);
     float v[NDIM];
 #pragma unroll
-    for (int c = 0; c < NDIM; ++c) v[c] = V[c * N + idx];
+    for (int c = 0; c < NDIM; ++c) v[c] = gld(V, c * N + idx);
     // div v at q (clamped central differences)
-    float div = 0.5f * (V[(NDIM - 1) * N + idx + up(xq, nx, 1)] - V[(NDIM - 1) * N + idx - dn(xq, 1)]);
-    div += 0.5f * (V[(NDIM - 2) * N + idx + up(yq, ny, nx)] - V[(NDIM - 2) * N + idx - dn(yq, nx)]);
-    if (NDIM == 3) div += 0.5f * (V[idx + up(zq, nz, sxy)] - V[idx - dn(zq, sxy)]);
-    float dx = -dt * v[NDIM - 1], dy = -dt * v[NDIM - 2];
-    dm = fmaxf(dm, fmaxf(fabsf(dx), fabsf(dy)));
+    const float* Vx = V + (NDIM - 1) * N;
+    const float* Vy = V + (NDIM - 2) * N;
+    float div = 0.5f * (gld(Vx, idx + (unsigned)up(xq, nx, 1)) - gld(Vx, idx - (unsigned)dn(xq, 1)));
+    div += 0.5f * (gld(Vy, idx + (unsigned)up(yq, ny, nx)) - gld(Vy, idx - (unsigned)dn(yq, nx)));
+    if (NDIM == 3) div += 0.5f * (gld(V, idx + (unsigned)up(zq, nz, sxy)) - gld(V, idx - (unsigned)dn(zq, sxy)));
+    const float dx = -dt * v[NDIM - 1], dy = -dt * v[NDIM - 2];
     const Axis ax = foot_axis(xq, dx, nx);
     const Axis ay = foot_axis(yq, dy, ny);
+    float dmq = fmaxf(fabsf(dx), fabsf(dy));
     float Ih, zh;
     if (NDIM == 2) {
-      const int c00 = ay.i * nx + ax.i;
+      const unsigned c00 = (unsigned)(ay.i * nx + ax.i);
       const float wy0 = 1.f - ay.f, wy1 = ay.f, wx0 = 1.f - ax.f, wx1 = ax.f;
-      Ih = wy0 * (wx0 * I[c00] + wx1 * I[c00 + 1]) + wy1 * (wx0 * I[c00 + nx] + wx1 * I[c00 + nx + 1]);
-      zh = wy0 * (wx0 * Z[c00] + wx1 * Z[c00 + 1]) + wy1 * (wx0 * Z[c00 + nx] + wx1 * Z[c00 + nx + 1]);
+      const unsigned c10 = c00 + (unsigned)nx;
+      Ih = wy0 * (wx0 * gld(I, c00) + wx1 * gld(I, c00 + 1)) + wy1 * (wx0 * gld(I, c10) + wx1 * gld(I, c10 + 1));
+      zh = wy0 * (wx0 * gld(Z, c00) + wx1 * gld(Z, c00 + 1)) + wy1 * (wx0 * gld(Z, c10) + wx1 * gld(Z, c10 + 1));
     } else {
       const float dz = -dt * v[0];
-      dm = fmaxf(dm, fabsf(dz));
+      dmq = fmaxf(dmq, fabsf(dz));
       const Axis az = foot_axis(zq, dz, nz);
-      const int c000 = az.i * sxy + ay.i * nx + ax.i;
+      const unsigned c000 = (unsigned)(az.i * (int)sxy + ay.i * nx + ax.i);
       const float wz0 = 1.f - az.f, wz1 = az.f, wy0 = 1.f - ay.f, wy1 = ay.f, wx0 = 1.f - ax.f, wx1 = ax.f;
-      const int c010 = c000 + nx, c100 = c000 + sxy, c110 = c100 + nx;
-      Ih = wz0 * (wy0 * (wx0 * I[c000] + wx1 * I[c000 + 1]) + wy1 * (wx0 * I[c010] + wx1 * I[c010 + 1])) +
-           wz1 * (wy0 * (wx0 * I[c100] + wx1 * I[c100 + 1]) + wy1 * (wx0 * I[c110] + wx1 * I[c110 + 1]));
-      zh = wz0 * (wy0 * (wx0 * Z[c000] + wx1 * Z[c000 + 1]) + wy1 * (wx0 * Z[c010] + wx1 * Z[c010 + 1])) +
-           wz1 * (wy0 * (wx0 * Z[c100] + wx1 * Z[c100 + 1]) + wy1 * (wx0 * Z[c110] + wx1 * Z[c110 + 1]));
+      const unsigned c010 = c000 + nx, c100 = c000 + sxy, c110 = c100 + nx;
+      Ih = wz0 * (wy0 * (wx0 * gld(I, c000) + wx1 * gld(I, c000 + 1)) + wy1 * (wx0 * gld(I, c010) + wx1 * gld(I, c010 + 1))) +
+           wz1 * (wy0 * (wx0 * gld(I, c100) + wx1 * gld(I, c100 + 1)) + wy1 * (wx0 * gld(I, c110) + wx1 * gld(I, c110 + 1)));
+      zh = wz0 * (wy0 * (wx0 * gld(Z, c000) + wx1 * gld(Z, c000 + 1)) + wy1 * (wx0 * gld(Z, c010) + wx1 * gld(Z, c010 + 1))) +
+           wz1 * (wy0 * (wx0 * gld(Z, c100) + wx1 * gld(Z, c100 + 1)) + wy1 * (wx0 * gld(Z, c110) + wx1 * gld(Z, c110 + 1)));
     }
     const float In = fmaf(rdt, zh, Ih);
     const float zn = zh * (1.f - dt * div);
+    if (!inside) continue;
+    dm = fmaxf(dm, dmq);
     if (Io) {
-      Io[idx] = In;
-      Io[N + idx] = zn;
+      gst(Io, idx, In);
+      gst(Io, N + idx, zn);
     }
     if (A.red_reg) {
       // -<m_0, v_0> + rho |p0|^2 at q, with m_c = z D_c I
-      const float zq0 = Z[idx];
+      const float zq0 = gld(Z, idx);
       float g[NDIM];
-      g[NDIM - 1] = 0.5f * (I[idx + up(xq, nx, 1)] - I[idx - dn(xq, 1)]);
-      g[NDIM - 2] = 0.5f * (I[idx + up(yq, ny, nx)] - I[idx - dn(yq, nx)]);
-      if (NDIM == 3) g[0] = 0.5f * (I[idx + up(zq, nz, sxy)] - I[idx - dn(zq, sxy)]);
+      g[NDIM - 1] = 0.5f * (gld(I, idx + (unsigned)up(xq, nx, 1)) - gld(I, idx - (unsigned)dn(xq, 1)));
+      g[NDIM - 2] = 0.5f * (gld(I, idx + (unsigned)up(yq, ny, nx)) - gld(I, idx - (unsigned)dn(yq, nx)));
+      if (NDIM == 3) g[0] = 0.5f * (gld(I, idx + (unsigned)up(zq, nz, sxy)) - gld(I, idx - (unsigned)dn(zq, sxy)));
       float mv = 0.f;
 #pragma unroll
       for (int c = 0; c < NDIM; ++c) mv = fmaf(zq0 * g[c], v[c], mv);
@@ -356,63 +428,62 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
 // H = floor(D) + 1 cells of its arrival point, so only the q in P +- H reach
 // P. Phase 1 visits those q and leaves one record per q in LDS (cell of the
 // foot, its fractions, Ib and zh_bar), plus div_bar on P +- 1 and the
-// foot-point part of vbar on P. Phase 2 forms Interp^T at each p of P as a
-// gather over the (2H+1)^d candidate q around it, in a fixed order: no
-// atomics, deterministic, each output written once. For D >= HS (or when
-// forced) the block instead scatters its own q with global atomics into the
-// accumulator, which the previous adjoint step (or the last forward step)
-// cleared.
+// foot-point part of vbar of the thread's own outputs. Phase 2 forms
+// Interp^T at each p of P as a gather over the (2H+1)^d candidate q around
+// it, in a fixed order: no atomics, deterministic, each output written once.
+// For D >= HS (or when forced) the block instead scatters its own q with
+// global atomics into the accumulator, which the previous adjoint step (or
+// the last forward step) cleared.
 __device__ __forceinline__ float diffT_lds(const float* g, int b, int j, int n, int s) {
   if (j == 0) return -0.5f * (g[b] + g[b + s]);
   if (j == n - 1) return 0.5f * (g[b - s] + g[b]);
   return 0.5f * (g[b - s] - g[b + s]);
 }
 
-// Phase-1 work for one arrival point q (local coordinates l* relative to P):
-// its record, div_bar (on P +- 1), the global scatter (fallback mode) and,
-// for q in P, the foot-point part of vbar (returned in vq).
+// Phase-1 work for one arrival point (local coordinates l* relative to P,
+// record slot li): its record, div_bar (on P +- 1), the global scatter
+// (fallback mode) and, for q in P, the foot-point part of vbar (into vq).
 template <int NDIM>
 __device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool inP, bool gmode, int x0, int y0,
-                                          int z0, int nx, int ny, int nz, int N, float dt, float rdt,
+                                          int z0, int nx, int ny, int nz, unsigned N, float dt, float rdt,
                                           const float* __restrict__ V, const float* __restrict__ I,
                                           const float* __restrict__ Z, const float* __restrict__ AB,
                                           float* __restrict__ SI, float* __restrict__ SZ, int* rcell,
                                           float (*rf)[ADJ_NQ<NDIM>()], float* rib, float* rzb, float* dbar,
                                           float vq[NDIM]) {
-  constexpr int PX = NDIM == 2 ? ADJ2_X : ADJ3_X;
-  constexpr int PY = NDIM == 2 ? ADJ2_Y : ADJ3_Y;
-  constexpr int PZ = NDIM == 2 ? 1 : ADJ3_Z;
-  constexpr int HS = NDIM == 2 ? ADJ2_HS : ADJ3_HS;
-  constexpr int DX = PX + 2, DY = PY + 2;
+  using B = Blk<NDIM>;
+  constexpr int DX = B::X + 2, DY = B::Y + 2;
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int NC = NDIM == 3 ? 8 : 4;
-  constexpr int COFF = 2 * HS;
-  const int sxy = nx * ny;
+  constexpr int COFF = 2 * B::HS;
+  const unsigned sxy = (unsigned)(nx * ny);
   const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
-  const bool inP1 = lx >= -1 && lx <= PX && ly >= -1 && ly <= PY && (NDIM == 2 || (lz >= -1 && lz <= PZ));
-  const int idx = (qz * ny + qy) * nx + qx;
-  float div = 0.5f * (V[(NDIM - 1) * N + idx + up(qx, nx, 1)] - V[(NDIM - 1) * N + idx - dn(qx, 1)]);
-  div += 0.5f * (V[(NDIM - 2) * N + idx + up(qy, ny, nx)] - V[(NDIM - 2) * N + idx - dn(qy, nx)]);
-  if (NDIM == 3) div += 0.5f * (V[idx + up(qz, nz, sxy)] - V[idx - dn(qz, sxy)]);
-  const float Ib = AB[idx];
-  const float zb = AB[N + idx];
-  const Axis ax = foot_axis(qx, -dt * V[(NDIM - 1) * N + idx], nx);
-  const Axis ay = foot_axis(qy, -dt * V[(NDIM - 2) * N + idx], ny);
+  const bool inP1 = lx >= -1 && lx <= B::X && ly >= -1 && ly <= B::Y && (NDIM == 2 || (lz >= -1 && lz <= B::Z));
+  const unsigned idx = (unsigned)((qz * ny + qy) * nx + qx);
+  const float* Vx = V + (NDIM - 1) * N;
+  const float* Vy = V + (NDIM - 2) * N;
+  float div = 0.5f * (gld(Vx, idx + (unsigned)up(qx, nx, 1)) - gld(Vx, idx - (unsigned)dn(qx, 1)));
+  div += 0.5f * (gld(Vy, idx + (unsigned)up(qy, ny, nx)) - gld(Vy, idx - (unsigned)dn(qy, nx)));
+  if (NDIM == 3) div += 0.5f * (gld(V, idx + (unsigned)up(qz, nz, sxy)) - gld(V, idx - (unsigned)dn(qz, sxy)));
+  const float Ib = gld(AB, idx);
+  const float zb = gld(AB, N + idx);
+  const Axis ax = foot_axis(qx, -dt * gld(Vx, idx), nx);
+  const Axis ay = foot_axis(qy, -dt * gld(Vy, idx), ny);
   Axis az;
   if (NDIM == 3) {
-    az = foot_axis(qz, -dt * V[idx], nz);
+    az = foot_axis(qz, -dt * gld(V, idx), nz);
   } else {
     az.i = 0; az.f = 0.f; az.live = 0.f;
   }
   const float wz[2] = {1.f - az.f, az.f}, wy[2] = {1.f - ay.f, ay.f}, wx[2] = {1.f - ax.f, ax.f};
-  const int c0 = az.i * sxy + ay.i * nx + ax.i;
+  const unsigned c0 = (unsigned)(az.i * (int)sxy + ay.i * nx + ax.i);
   float zv[NC], iv[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-    const int g = c0 + bz * sxy + by * nx + bx;
-    zv[k] = Z[g];
-    iv[k] = inP ? I[g] : 0.f;
+    const unsigned g = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
+    zv[k] = gld(Z, g);
+    if (inP) iv[k] = gld(I, g);
   }
   float zh = 0.f;
 #pragma unroll
@@ -436,7 +507,7 @@ __device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool i
       for (int k = 0; k < NC; ++k) {
         const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
         const float w = (NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx];
-        const int g = c0 + bz * sxy + by * nx + bx;
+        const unsigned g = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
         unsafeAtomicAdd(SI + g, w * Ib);
         unsafeAtomicAdd(SZ + g, w * zhb);
       }
@@ -466,13 +537,8 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
                                                      const float* __restrict__ Vg, const float* __restrict__ stg,
                                                      const float* __restrict__ abg, float* __restrict__ scg,
                                                      float* __restrict__ vbg, AdjArgs A) {
-  constexpr int PX = NDIM == 2 ? ADJ2_X : ADJ3_X;
-  constexpr int PY = NDIM == 2 ? ADJ2_Y : ADJ3_Y;
-  constexpr int PZ = NDIM == 2 ? 1 : ADJ3_Z;
-  constexpr int HS = NDIM == 2 ? ADJ2_HS : ADJ3_HS;   // gather mode handles D < HS
-  constexpr int NP = PX * PY * PZ;
-  constexpr int PPT = NP / NT;                        // outputs per thread
-  static_assert(NP % NT == 0, "tile must be a multiple of the block");
+  using B = Blk<NDIM>;
+  constexpr int PX = B::X, PY = B::Y, PZ = B::Z, HS = B::HS, PPT = B::PPT;
   // P +- 1 (div_bar) and P +- HS (arrival points that may reach P)
   constexpr int DX = PX + 2, DY = PY + 2, DZ = NDIM == 3 ? PZ + 2 : 1;
   constexpr int QX = PX + 2 * HS, QY = PY + 2 * HS;
@@ -487,7 +553,7 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   const Tile tl = tla[xcd_tile(gridDim.x)];
   const PairDev& P = pd[tl.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int N = (int)P.N;
+  const unsigned N = (unsigned)P.N;
   const float dt = P.dt, rdt = P.rho * P.dt;
   const int x0 = tl.a, y0 = tl.b, z0 = tl.c;
   const float D = __uint_as_float(A.dmax[(long long)tl.pair * A.T + A.t]);
@@ -505,8 +571,8 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   float vq[PPT][NDIM];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int li = threadIdx.x + k * NT;
-    const int lx = li % PX, ly = (li / PX) % PY, lz = li / (PX * PY);
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
     const int r = ((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS);
 #pragma unroll
     for (int c = 0; c < NDIM; ++c) vq[k][c] = 0.f;
@@ -516,9 +582,8 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
     else
       rcell[r] = -1;
   }
-  // phase 1b: the halo points P +- H around P (records and div_bar only)
+  // phase 1b: the halo points around P (records and div_bar only)
   const int hq = gmode ? H : 1;
-#pragma unroll 2
   for (int li = threadIdx.x; li < NQ; li += NT) {
     const int lx = li % QX - HS, ly = (li / QX) % QY - HS, lz = NDIM == 3 ? li / (QX * QY) - HS : 0;
     const bool inP = lx >= 0 && lx < PX && ly >= 0 && ly < PY && lz >= 0 && lz < PZ;
@@ -540,15 +605,15 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   // phase 2: vbar and the gathered transpose of the interpolation
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int li = threadIdx.x + k * NT;
-    const int lx = li % PX, ly = (li / PX) % PY, lz = li / (PX * PY);
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
     const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
-    if (qx >= nx || qy >= ny || (NDIM == 3 && qz >= nz)) continue;
-    const int idx = (qz * ny + qy) * nx + qx;
+    if (qx >= nx || qy >= ny || qz >= nz) continue;
+    const unsigned idx = (unsigned)((qz * ny + qy) * nx + qx);
     const int b = ((lz + ZO) * DY + (ly + 1)) * DX + (lx + 1);
-    VB[(NDIM - 1) * N + idx] = vq[k][NDIM - 1] + diffT_lds(dbar, b, qx, nx, 1);
-    VB[(NDIM - 2) * N + idx] = vq[k][NDIM - 2] + diffT_lds(dbar, b, qy, ny, DX);
-    if (NDIM == 3) VB[idx] = vq[k][0] + diffT_lds(dbar, b, qz, nz, DX * DY);
+    gst(VB, (NDIM - 1) * N + idx, vq[k][NDIM - 1] + diffT_lds(dbar, b, qx, nx, 1));
+    gst(VB, (NDIM - 2) * N + idx, vq[k][NDIM - 2] + diffT_lds(dbar, b, qy, ny, DX));
+    if (NDIM == 3) gst(VB, idx, vq[k][0] + diffT_lds(dbar, b, qz, nz, DX * DY));
     if (gmode) {
       // Interp^T at p: sum over candidate arrival points q = p + (oz, oy, ox)
       float accI = 0.f, accZ = 0.f;
@@ -568,8 +633,8 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
             accI = fmaf(w, rib[r], accI);
             accZ = fmaf(w, rzb[r], accZ);
           }
-      SI[idx] = accI;
-      SZ[idx] = accZ;
+      gst(SI, idx, accI);
+      gst(SZ, idx, accZ);
     }
   }
 }
@@ -581,15 +646,15 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
 // At t = 0 only dH/dp0 = zbar_0 + 2 lambda rho p0 is written. The scatter
 // accumulator is cleared when the next (earlier) step scatters with global
 // atomics.
-
 template <int NDIM>
 __global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                  const float* __restrict__ mbg, const float* __restrict__ stg,
                                                  float* __restrict__ scg, float* __restrict__ abg, EpiArgs A) {
+  using B = Blk<NDIM>;
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int N = (int)P.N;
+  const unsigned N = (unsigned)P.N;
   const int sxy = nx * ny;
   const float* __restrict__ MB = mbg + NDIM * P.off;
   const float* __restrict__ I = stg + 2 * P.off;
@@ -599,49 +664,52 @@ __global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd,
   bool clear = false;
   if (!A.first) {
     const float Dn = __uint_as_float(A.dmax[(long long)t.pair * A.T + A.t - 1]);
-    clear = A.force_global || !(Dn < (float)(NDIM == 2 ? ADJ2_HS : ADJ3_HS));
+    clear = A.force_global || !(Dn < (float)B::HS);
   }
 #pragma unroll
-  for (int k = 0; k < ELEM / NT; ++k) {
-    const int j = threadIdx.x + k * NT;
-    if (j >= t.b) continue;
-    const int idx = t.a + j;
-    const int xq = idx % nx;
-    const int yq = (idx / nx) % ny;
-    const int zq = idx / sxy;
+  for (int k = 0; k < B::PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    const bool inside = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
+    const int q[3] = {min(t.c + lz, nz - 1), min(t.b + ly, ny - 1), min(t.a + lx, nx - 1)};
     const int n[3] = {nz, ny, nx};
-    const int q[3] = {zq, yq, xq};
     const int s[3] = {sxy, nx, 1};
-    float zbar = SZ[idx];
-    float Ibar = SI[idx];
+    const unsigned idx = (unsigned)((q[0] * ny + q[1]) * nx + q[2]);
+    float zbar = gld(SZ, idx);
+    float Ibar = gld(SI, idx);
 #pragma unroll
     for (int c = 0; c < NDIM; ++c) {
       const int a = 3 - NDIM + c;  // geometric axis of channel c
       const float* M = MB + c * N;
-      const int sp = up(q[a], n[a], s[a]), sm = dn(q[a], s[a]);
-      zbar = fmaf(M[idx], 0.5f * (I[idx + sp] - I[idx - sm]), zbar);
+      const unsigned sp = (unsigned)up(q[a], n[a], s[a]), sm = (unsigned)dn(q[a], s[a]);
+      const float m0 = gld(M, idx);
+      zbar = fmaf(m0, 0.5f * (gld(I, idx + sp) - gld(I, idx - sm)), zbar);
       if (!A.first) {
         // D^T (z m) at q along axis a
         float dT;
+        const float zc = gld(Z, idx);
+        const float zmu = gld(Z, idx + sp) * gld(M, idx + sp);   // clamped neighbours
+        const float zmd = gld(Z, idx - sm) * gld(M, idx - sm);
         if (q[a] == 0)
-          dT = -0.5f * (Z[idx] * M[idx] + Z[idx + s[a]] * M[idx + s[a]]);
+          dT = -0.5f * (zc * m0 + zmu);
         else if (q[a] == n[a] - 1)
-          dT = 0.5f * (Z[idx - s[a]] * M[idx - s[a]] + Z[idx] * M[idx]);
+          dT = 0.5f * (zmd + zc * m0);
         else
-          dT = 0.5f * (Z[idx - s[a]] * M[idx - s[a]] - Z[idx + s[a]] * M[idx + s[a]]);
+          dT = 0.5f * (zmd - zmu);
         Ibar += dT;
       }
     }
+    if (!inside) continue;
     if (A.first) {
-      if (P.outG) P.outG[idx] = fmaf(2.f * P.lam * P.rho, Z[idx], zbar);
+      if (P.outG) gst(P.outG, idx, fmaf(2.f * P.lam * P.rho, gld(Z, idx), zbar));
     } else {
       float* __restrict__ AB = abg + 2 * P.off;
-      AB[idx] = Ibar;
-      AB[N + idx] = zbar;
+      gst(AB, idx, Ibar);
+      gst(AB, N + idx, zbar);
     }
     if (clear) {
-      SI[idx] = 0.f;
-      SZ[idx] = 0.f;
+      gst(SI, idx, 0.f);
+      gst(SZ, idx, 0.f);
     }
   }
 }
@@ -680,8 +748,9 @@ hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s) 
   return post();
 }
 
-hipError_t launch_init(const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s) {
-  k_init<<<nt, NT, 0, s>>>(pd, tl, st);
+hipError_t launch_init(int ndim, const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s) {
+  if (ndim == 2) k_init<2><<<nt, NT, 0, s>>>(pd, tl, st);
+  else k_init<3><<<nt, NT, 0, s>>>(pd, tl, st);
   return post();
 }
 

@@ -46,11 +46,11 @@ enum Op { OP_FORWARD = 0, OP_COST = 1, OP_GRAD = 2 };
 struct Wave {
   std::vector<int> ids;
   std::vector<PairDev> pdev;
-  std::vector<Tile> te, tx, ty, tz, ta;
+  std::vector<Tile> tb, tx, ty, tz;
   long long ntot = 0;                // padded voxel total
   size_t lds_x = 0, lds_y = 0, lds_z = 0;
   // header offsets (bytes from the workspace base)
-  size_t o_pd = 0, o_te = 0, o_tx = 0, o_ty = 0, o_tz = 0, o_ta = 0, o_dmax = 0, o_rreg = 0, o_rssd = 0;
+  size_t o_pd = 0, o_tb = 0, o_tx = 0, o_ty = 0, o_tz = 0, o_dmax = 0, o_rreg = 0, o_rssd = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
 };
@@ -213,7 +213,7 @@ shoot_status validate(const shoot_pair* pairs, int32_t n, int32_t T) {
 
 // Builds descriptors and tile lists of one wave (header offsets are set later).
 void build_wave(shoot_plan_s* p, Wave& w) {
-  w.pdev.clear(); w.te.clear(); w.tx.clear(); w.ty.clear(); w.tz.clear(); w.ta.clear();
+  w.pdev.clear(); w.tb.clear(); w.tx.clear(); w.ty.clear(); w.tz.clear();
   long long off = 0;
   w.lds_x = w.lds_y = w.lds_z = 0;
   for (size_t li = 0; li < w.ids.size(); ++li) {
@@ -235,11 +235,16 @@ void build_wave(shoot_plan_s* p, Wave& w) {
     P.outI = q.out_image; P.outZ = q.out_momentum; P.outG = q.out_grad; P.outCost = q.out_cost;
     fill_taps(P, q.sigma);
     const int pi = (int)li;
-    // elementwise tiles
-    P.elem_first = (int)w.te.size();
-    for (long long a = 0; a < P.N; a += ELEM)
-      w.te.push_back(Tile{pi, (int)a, (int)std::min<long long>(ELEM, P.N - a), 0});
-    P.elem_count = (int)w.te.size() - P.elem_first;
+    // block tiles (init, advect, adjoint, epilogue); cost partials are per block tile
+    P.elem_first = (int)w.tb.size();
+    {
+      const int BX = p->ndim == 2 ? BLK2_X : BLK3_X, BY = p->ndim == 2 ? BLK2_Y : BLK3_Y;
+      const int BZ = p->ndim == 2 ? 1 : BLK3_Z;
+      for (int z0 = 0; z0 < P.nz; z0 += BZ)
+        for (int y0 = 0; y0 < P.ny; y0 += BY)
+          for (int x0 = 0; x0 < P.nx; x0 += BX) w.tb.push_back(Tile{pi, x0, y0, z0});
+    }
+    P.elem_count = (int)w.tb.size() - P.elem_first;
     // x-pass tiles: rows of the pair; ~512 groups of four outputs per block,
     // within the LDS budget
     const size_t rb = xpass_row_bytes(p->ndim, P.nx, P.ntap4);
@@ -265,14 +270,6 @@ void build_wave(shoot_plan_s* p, Wave& w) {
           for (int s0 = 0; s0 < P.nz; s0 += SSEG) w.tz.push_back(Tile{pi, x0, o, s0});
       w.lds_z = std::max(w.lds_z, sb);
     }
-    // adjoint tiles
-    {
-      const int AX = p->ndim == 2 ? ADJ2_X : ADJ3_X, AY = p->ndim == 2 ? ADJ2_Y : ADJ3_Y;
-      const int AZ = p->ndim == 2 ? 1 : ADJ3_Z;
-      for (int z0 = 0; z0 < P.nz; z0 += AZ)
-        for (int y0 = 0; y0 < P.ny; y0 += AY)
-          for (int x0 = 0; x0 < P.nx; x0 += AX) w.ta.push_back(Tile{pi, x0, y0, z0});
-    }
     w.pdev.push_back(P);
   }
   w.ntot = off;
@@ -283,14 +280,13 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   size_t o = base;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, ALIGN); return r; };
   w.o_pd = take(w.pdev.size() * sizeof(PairDev));
-  w.o_te = take(w.te.size() * sizeof(Tile));
+  w.o_tb = take(w.tb.size() * sizeof(Tile));
   w.o_tx = take(w.tx.size() * sizeof(Tile));
   w.o_ty = take(w.ty.size() * sizeof(Tile));
   w.o_tz = take(w.tz.size() * sizeof(Tile));
-  w.o_ta = take(w.ta.size() * sizeof(Tile));
   w.o_dmax = take(w.pdev.size() * (size_t)p->T * sizeof(unsigned));
-  w.o_rreg = take(w.te.size() * sizeof(float));
-  w.o_rssd = take(w.te.size() * sizeof(float));
+  w.o_rreg = take(w.tb.size() * sizeof(float));
+  w.o_rssd = take(w.tb.size() * sizeof(float));
   w.header_bytes = o - base;
   return o;
 }
@@ -302,8 +298,8 @@ struct Ctx {
   Wave* w;
   hipStream_t s;
   const PairDev* pd;
-  const Tile *te, *tx, *ty, *tz, *ta;
-  int nte, ntx, nty, ntz, nta;
+  const Tile *tb, *tx, *ty, *tz;
+  int ntb, ntx, nty, ntz;
   unsigned* dmax;
   float *rreg, *rssd;
   float *st, *vs, *u, *u2, *ab, *sc, *vb;
@@ -316,11 +312,10 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   c.p = p; c.w = &w; c.s = s;
   char* b = p->ws;
   c.pd = (const PairDev*)(b + w.o_pd);
-  c.te = (const Tile*)(b + w.o_te); c.nte = (int)w.te.size();
+  c.tb = (const Tile*)(b + w.o_tb); c.ntb = (int)w.tb.size();
   c.tx = (const Tile*)(b + w.o_tx); c.ntx = (int)w.tx.size();
   c.ty = (const Tile*)(b + w.o_ty); c.nty = (int)w.ty.size();
   c.tz = (const Tile*)(b + w.o_tz); c.ntz = (int)w.tz.size();
-  c.ta = (const Tile*)(b + w.o_ta); c.nta = (int)w.ta.size();
   c.dmax = (unsigned*)(b + w.o_dmax);
   c.rreg = (float*)(b + w.o_rreg);
   c.rssd = (float*)(b + w.o_rssd);
@@ -367,7 +362,7 @@ hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
   if (e != hipSuccess) return e;
   const int T = c.p->T;
   AdvectArgs a{};
-  a.pd = c.pd; a.tl = c.te; a.V = VS(c, t); a.st = ST(c, t);
+  a.pd = c.pd; a.tl = c.tb; a.V = VS(c, t); a.st = ST(c, t);
   a.st_out = (store && t + 1 < T) ? ST(c, t + 1) : nullptr;
   a.T = T; a.t = t;
   a.dmax = first_pass ? c.dmax : nullptr;
@@ -375,14 +370,14 @@ hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
   a.red_reg = (first_pass && t == 0) ? c.rreg : nullptr;
   a.red_ssd = (first_pass && t == T - 1) ? c.rssd : nullptr;
   if (a.last && op == OP_GRAD) { a.ab_out = AB(c, T); a.sc_zero = c.sc; }
-  LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.nte, a, c.s));
+  LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.ntb, a, c.s));
   return hipSuccess;
 }
 
 hipError_t run_forward(const Ctx& c, int op) {
   const int T = c.p->T;
   LAUNCH(KI_FILL, launch_fill_u32(c.dmax, (long long)c.w->pdev.size() * T, 0u, c.s));
-  LAUNCH(KI_INIT, launch_init(c.pd, c.te, c.nte, ST(c, 0), c.s));
+  LAUNCH(KI_INIT, launch_init(c.p->ndim, c.pd, c.tb, c.ntb, ST(c, 0), c.s));
   for (int t = 0; t < T; ++t) {
     hipError_t e = fwd_step(c, t, true, op, true);
     if (e != hipSuccess) return e;
@@ -396,10 +391,10 @@ hipError_t bwd_step(const Ctx& c, int t) {
   const int nd = c.p->ndim;
   const int force = (c.p->flags & SHOOT_FORCE_GLOBAL_SCATTER) ? 1 : 0;
   AdjArgs a{};
-  a.pd = c.pd; a.tl = c.ta; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
+  a.pd = c.pd; a.tl = c.tb; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
   a.sc = c.sc; a.vb = c.vb;
   a.dmax = c.dmax; a.T = c.p->T; a.t = t; a.force_global = force;
-  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.nta, a, c.s));
+  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.ntb, a, c.s));
   // mbar = -G vbar (+ -2 lambda v_0 at t = 0), written back into vb
   LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.w->lds_x, c.vb, c.u, c.s));
   const float* extra = t == 0 ? VS(c, 0) : nullptr;
@@ -410,11 +405,11 @@ hipError_t bwd_step(const Ctx& c, int t) {
     LAUNCH(KI_SPASS_MBAR, launch_spass(3, true, 2, c.pd, c.tz, c.ntz, c.w->lds_z, c.u2, c.vb, extra, c.s));
   }
   EpiArgs ep{};
-  ep.pd = c.pd; ep.tl = c.te; ep.mb = c.vb; ep.st = ST(c, t); ep.sc = c.sc;
+  ep.pd = c.pd; ep.tl = c.tb; ep.mb = c.vb; ep.st = ST(c, t); ep.sc = c.sc;
   ep.ab_out = t > 0 ? AB(c, t) : nullptr;
   ep.dmax = c.dmax; ep.T = c.p->T; ep.t = t; ep.force_global = force;
   ep.first = t == 0 ? 1 : 0;
-  LAUNCH(KI_EPILOGUE, launch_epilogue(nd, c.nte, ep, c.s));
+  LAUNCH(KI_EPILOGUE, launch_epilogue(nd, c.ntb, ep, c.s));
   return hipSuccess;
 }
 
@@ -594,11 +589,10 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
       if (bytes) std::memcpy(p->blob.data() + off, src, bytes);
     };
     put(w.o_pd, w.pdev.data(), w.pdev.size() * sizeof(PairDev));
-    put(w.o_te, w.te.data(), w.te.size() * sizeof(Tile));
+    put(w.o_tb, w.tb.data(), w.tb.size() * sizeof(Tile));
     put(w.o_tx, w.tx.data(), w.tx.size() * sizeof(Tile));
     put(w.o_ty, w.ty.data(), w.ty.size() * sizeof(Tile));
     put(w.o_tz, w.tz.data(), w.tz.size() * sizeof(Tile));
-    put(w.o_ta, w.ta.data(), w.ta.size() * sizeof(Tile));
   }
   *out = p;
   g_err.clear();

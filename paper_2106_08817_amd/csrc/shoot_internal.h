@@ -14,22 +14,20 @@ constexpr int WPAD = 4 * ((2 * RMAX + 1 + 3) / 4);   // 64
 
 // Threads per block for every kernel.
 constexpr int NT = 256;
-// Voxels per elementwise tile (each thread handles ELEM / NT of them).
-constexpr int ELEM = 1024;
 // Strided-pass tile: 64 lanes along x, NT/64 waves along the pass axis, each
 // thread produces SRB consecutive outputs along it.
 constexpr int SRB = 16;
 constexpr int SSEG = (NT / 64) * SRB;                  // 64 outputs per tile
-// Adjoint-advection tiles (outputs owned by one block) and the per-step
-// displacement bound (pixels, exclusive) below which a block accumulates in
-// LDS from staged I, z; above it the block falls back to global atomics.
-constexpr int ADJ2_X = 64, ADJ2_Y = 16, ADJ2_HS = 2;
-constexpr int ADJ3_X = 32, ADJ3_Y = 8, ADJ3_Z = 4, ADJ3_HS = 1;
+// Block tiles of the elementwise kernels (init, advect, adjoint, epilogue):
+// 1024 voxels, four per thread, x fastest. The adjoint gathers in LDS while
+// the per-step displacement bound is below BLK*_HS pixels.
+constexpr int BLK2_X = 32, BLK2_Y = 32, BLK2_HS = 2;
+constexpr int BLK3_X = 32, BLK3_Y = 8, BLK3_Z = 4, BLK3_HS = 1;
 // arrival points staged per adjoint tile: the tile grown by the bound on each side
 template <int NDIM>
 constexpr int ADJ_NQ() {
-  return NDIM == 2 ? (ADJ2_X + 2 * ADJ2_HS) * (ADJ2_Y + 2 * ADJ2_HS)
-                   : (ADJ3_X + 2 * ADJ3_HS) * (ADJ3_Y + 2 * ADJ3_HS) * (ADJ3_Z + 2 * ADJ3_HS);
+  return NDIM == 2 ? (BLK2_X + 2 * BLK2_HS) * (BLK2_Y + 2 * BLK2_HS)
+                   : (BLK3_X + 2 * BLK3_HS) * (BLK3_Y + 2 * BLK3_HS) * (BLK3_Z + 2 * BLK3_HS);
 }
 
 // Per-pair descriptor, resident in the workspace. Geometry is stored as
@@ -40,8 +38,8 @@ struct alignas(16) PairDev {
   int r;          // Gaussian radius floor(3 sigma)
   int ntap4;      // ceil((2r + 1) / 4)
   int xrows;      // rows per x-pass tile for this pair
-  int elem_first; // index of this pair's first elementwise tile
-  int elem_count; // number of elementwise tiles of this pair
+  int elem_first; // index of this pair's first block tile
+  int elem_count; // number of block tiles of this pair
   long long off;  // voxel offset of the pair in the batch
   long long N;    // voxels
   float rho, lam, dt, pad_;
@@ -59,7 +57,7 @@ static_assert(sizeof(long long) == 8 && sizeof(void*) == 8, "LP64 expected");
 static_assert(__builtin_offsetof(PairDev, w) % 16 == 0, "taps must be 16-byte aligned");
 
 // Tile entry of a launch list. Meaning of a/b/c per kernel family:
-//   elementwise: a = first voxel, b = voxel count
+//   block tile : a = x0, b = y0, c = z0 (origin of a BLK tile)
 //   x-pass     : a = first row (rows are (z, y) flattened), b = row count
 //   y/z-pass   : a = first x, b = index along the third axis, c = first output
 struct alignas(16) Tile {
