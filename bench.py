@@ -52,14 +52,36 @@ def bytes_per_voxel(name: str, d: int) -> int:
         "spass_v": 2 * d,
         "spass_mbar": 2 * d,
         "advect": d + 2 + 2,             # read v, I, z; write I', z'
-        "advect_adjoint": (d + 2 + 2) + (2 + 1 + d),  # read v, I, z, Ibar', zbar'; write scatter, divbar, vbar
-        "divT": (1 + d) + d,
-        "epilogue": (d + 2 + 2) + (2 + 2),  # read mbar, I, z, scatter; write Ibar, zbar, clear scatter
+        "advect_adjoint": (d + 2 + 2) + (2 + d),  # read v, I, z, Ibar', zbar'; write Interp^T parts, vbar
+        "epilogue": (d + 2 + 2) + 2,     # read mbar, I, z, Interp^T parts; write Ibar, zbar
         "init": 4,
         "fill": 0,
         "finalize": 0,
     }
     return f * table.get(name, 0)
+
+
+# rocprofv3 kernel names -> kernel families of the profiling statistics
+def family_of(kernel_name: str) -> str:
+    n = kernel_name
+    if "k_adv_adj_tile" in n:
+        return "advect_adjoint"
+    if "k_advect" in n:
+        return "advect"
+    if "k_epilogue" in n:
+        return "epilogue"
+    if "k_xpass" in n:
+        return "xpass_gradmul" if "true>" in n else "xpass_plain"
+    if "k_spass" in n:
+        mode = n.split("k_spass<")[1].split(">")[0].split(",")[-1].strip()
+        return {"0": "spass_mid", "1": "spass_v", "2": "spass_mbar"}[mode]
+    if "k_init" in n:
+        return "init"
+    if "k_finalize" in n:
+        return "finalize"
+    if "k_fill_u32" in n:
+        return "fill"
+    return n
 
 
 def kernel_source_sha() -> str:
@@ -85,6 +107,73 @@ def measured_traffic(kernel: str, workload: str, launches_ref: int):
     if not entry or entry.get("source_sha") != kernel_source_sha():
         return None
     return entry.get("bytes_per_launch")
+
+
+def copy_probe(mbytes: int, reps: int) -> None:
+    """A plain device-to-device copy of known size, for calibrating the
+    FETCH_SIZE / WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+
+    n = mbytes * (1 << 20) // 4
+    a = torch.rand(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}))
+
+
+def write_traffic(workload: str, fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str,
+                  copy_bytes: int, path: str) -> None:
+    """Per-launch HBM traffic of every kernel family from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+    the same counter reads for a plain copy of known size; written to
+    profiles/traffic.json with the hash of the kernel sources."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        acc = defaultdict(list)
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == counter:
+                    acc[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return acc
+
+    def copy_kib(path, counter):
+        vals = [v for k, vs in per_kernel(path, counter).items() for v in vs
+                if "shoot::" not in k and max(vs) > 0.5 * copy_bytes / 1024]
+        return sorted(vals)[len(vals) // 2]
+
+    f_scale = copy_bytes / (1024.0 * copy_kib(copy_fetch_csv, "FETCH_SIZE"))
+    w_scale = copy_bytes / (1024.0 * copy_kib(copy_write_csv, "WRITE_SIZE"))
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    fam = defaultdict(lambda: {"fetch": [], "write": []})
+    for k, vs in fetch.items():
+        if "shoot::" in k:
+            fam[family_of(k)]["fetch"] += vs
+    for k, vs in write.items():
+        if "shoot::" in k:
+            fam[family_of(k)]["write"] += vs
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            rec = json.load(fh)
+    sha = kernel_source_sha()
+    out = {}
+    for name, d in fam.items():
+        if not d["fetch"] or not d["write"]:
+            continue
+        fb = 1024.0 * f_scale * sum(d["fetch"]) / len(d["fetch"])
+        wb = 1024.0 * w_scale * sum(d["write"]) / len(d["write"])
+        out[name] = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                     "dispatches": len(d["fetch"]), "source_sha": sha}
+    rec[workload] = out
+    rec["_calibration"] = {"copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale}
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
 
 
 def build_plan(workload, flags, torch, api):
@@ -139,7 +228,21 @@ def main():
     ap.add_argument("--no-unfused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0, help="extra plan flags (bit mask of SHOOT_*)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the full-store and single-pair lines")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="only run a plain copy of MB MiB (counter calibration) and exit")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="only turn rocprofv3 counter CSVs into profiles/traffic.json and exit")
+    ap.add_argument("--copy-mb", type=int, default=1024, help="size of the calibration copy (MiB)")
+    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
+
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 5)
+        return
+    if args.write_traffic:
+        write_traffic(args.workload, *args.write_traffic, args.copy_mb * (1 << 20), args.traffic_out)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -200,6 +303,30 @@ def main():
     print(f"[bench] dominant kernel {dom}: {dk['avg_us']:.1f} us/launch, {achieved:.0f} GB/s algorithmic",
           file=sys.stderr, flush=True)
 
+    extra = {}
+    if not args.no_extra:
+        fplan = build_plan(wl, api.SHOOT_FULL_STORE | args.flags, torch, api)
+        for _ in range(args.warmup):
+            fplan.grad()
+        fsecs = time_evals(fplan, args.steps, torch)
+        extra["full_store"] = {"value": vsteps * args.steps / fsecs, "unit": "voxel-steps/s",
+                               "ms_per_eval": 1000.0 * fsecs / args.steps,
+                               "note": "all T states kept (no recomputation); same kernels"}
+        fplan.close()
+        if args.workload != "c2":
+            w2 = synthetic.workload("c2", p0_kind="realistic")
+            p2 = build_plan(w2, args.flags, torch, api)
+            for _ in range(args.warmup):
+                p2.grad()
+            n2 = max(args.steps, 20)
+            s2 = time_evals(p2, n2, torch)
+            v2 = w2.voxel_steps
+            extra["single_pair_c2"] = {"evals_per_s": n2 / s2, "ms_per_eval": 1000.0 * s2 / n2,
+                                       "voxel_steps_per_s": v2 * n2 / s2,
+                                       "workload": "c2: " + WORKLOADS["c2"]}
+            p2.close()
+        print(f"[bench] extra: {json.dumps(extra)}", file=sys.stderr, flush=True)
+
     unfused = None
     if not args.no_unfused:
         uplan = build_plan(wl, api.SHOOT_UNFUSED, torch, api)
@@ -243,6 +370,7 @@ def main():
         "roofline": roofline,
         "unfused": unfused,
         "cpu_baseline": cpu,
+        "extra": extra,
         "kernels": kernels,
         "kernel_source_sha": kernel_source_sha(),
     }
