@@ -426,11 +426,12 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
 // A block owns a tile P of outputs. With D = max |dt v| of this pair and step
 // (recorded by the forward pass) every corner a foot touches lies within
 // H = floor(D) + 1 cells of its arrival point, so only the q in P +- H reach
-// P. Phase 1 visits those q and leaves one record per q in LDS (cell of the
-// foot, its fractions, Ib and zh_bar), plus div_bar on P +- 1 and the
+// P. Phase 1 visits those q and leaves one record per q in LDS (the foot's
+// clamped offset per axis, Ib and zh_bar), plus div_bar on P +- 1 and the
 // foot-point part of vbar of the thread's own outputs. Phase 2 forms
 // Interp^T at each p of P as a gather over the (2H+1)^d candidate q around
-// it, in a fixed order: no atomics, deterministic, each output written once.
+// it with hat weights, in a fixed order and without branches: no atomics,
+// deterministic, each output written once.
 // For D >= HS (or when forced) the block instead scatters its own q with
 // global atomics into the accumulator, which the previous adjoint step (or
 // the last forward step) cleared.
@@ -440,6 +441,36 @@ __device__ __forceinline__ float diffT_lds(const float* g, int b, int j, int n, 
   return 0.5f * (g[b - s] - g[b + s]);
 }
 
+// Record of one arrival point q for the gather: the foot's offset from q per
+// axis after clamping, e = clamp(q + d, 0, n - 1) - q, and the cotangents
+// (Ib, zh_bar). Linear interpolation gives q's corner q + o the weight
+// hat(e - o) = max(0, 1 - |e - o|) along each axis; for |e| < 1 that is
+// max(-e, 0), 1 - |e|, max(e, 0) at o = -1, 0, 1. 2-D keeps
+// (e_x, e_y, Ib, zh_bar) in one vector; 3-D keeps (e_x, e_y, e_z, Ib) and
+// zh_bar beside it.
+template <int NDIM>
+struct Rec {
+  vf4* v;
+  float* zb;  // 3-D only
+  __device__ __forceinline__ void put(int r, float ex, float ey, float ez, float ib, float zhb) const {
+    if (NDIM == 2) {
+      v[r] = vf4{ex, ey, ib, zhb};
+    } else {
+      v[r] = vf4{ex, ey, ez, ib};
+      zb[r] = zhb;
+    }
+  }
+  __device__ __forceinline__ void clear(int r) const { put(r, 0.f, 0.f, 0.f, 0.f, 0.f); }
+};
+
+// weight of a record toward its corner at offset O (|e| < 1)
+template <int O>
+__device__ __forceinline__ float tap3(float e) {
+  return O < 0 ? fmaxf(-e, 0.f) : (O == 0 ? 1.f - fabsf(e) : fmaxf(e, 0.f));
+}
+
+__device__ __forceinline__ float hat(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
+
 // Phase-1 work for one arrival point (local coordinates l* relative to P,
 // record slot li): its record, div_bar (on P +- 1), the global scatter
 // (fallback mode) and, for q in P, the foot-point part of vbar (into vq).
@@ -448,14 +479,12 @@ __device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool i
                                           int z0, int nx, int ny, int nz, unsigned N, float dt, float rdt,
                                           const float* __restrict__ V, const float* __restrict__ I,
                                           const float* __restrict__ Z, const float* __restrict__ AB,
-                                          float* __restrict__ SI, float* __restrict__ SZ, int* rcell,
-                                          float (*rf)[ADJ_NQ<NDIM>()], float* rib, float* rzb, float* dbar,
-                                          float vq[NDIM]) {
+                                          float* __restrict__ SI, float* __restrict__ SZ, const Rec<NDIM>& rec,
+                                          float* dbar, float vq[NDIM]) {
   using B = Blk<NDIM>;
   constexpr int DX = B::X + 2, DY = B::Y + 2;
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int NC = NDIM == 3 ? 8 : 4;
-  constexpr int COFF = 2 * B::HS;
   const unsigned sxy = (unsigned)(nx * ny);
   const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
   const bool inP1 = lx >= -1 && lx <= B::X && ly >= -1 && ly <= B::Y && (NDIM == 2 || (lz >= -1 && lz <= B::Z));
@@ -494,23 +523,16 @@ __device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool i
   const float zhb = fmaf(rdt, Ib, (1.f - dt * div) * zb);
   if (inP1) dbar[((lz + ZO) * DY + (ly + 1)) * DX + (lx + 1)] = -dt * zh * zb;
   if (gmode) {
-    rcell[li] = (ax.i - x0 + COFF) | ((ay.i - y0 + COFF) << 8) | ((NDIM == 3 ? az.i - z0 + COFF : 0) << 16);
-    rf[NDIM - 1][li] = ax.f;
-    rf[NDIM - 2][li] = ay.f;
-    if (NDIM == 3) rf[0][li] = az.f;
-    rib[li] = Ib;
-    rzb[li] = zhb;
-  } else {
-    rcell[li] = -1;
-    if (inP) {
+    rec.put(li, (float)(ax.i - qx) + ax.f, (float)(ay.i - qy) + ay.f, NDIM == 3 ? (float)(az.i - qz) + az.f : 0.f,
+            Ib, zhb);
+  } else if (inP) {
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-        const float w = (NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx];
-        const unsigned g = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
-        unsafeAtomicAdd(SI + g, w * Ib);
-        unsafeAtomicAdd(SZ + g, w * zhb);
-      }
+    for (int k = 0; k < NC; ++k) {
+      const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
+      const float w = (NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx];
+      const unsigned g = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
+      unsafeAtomicAdd(SI + g, w * Ib);
+      unsafeAtomicAdd(SZ + g, w * zhb);
     }
   }
   if (inP) {
@@ -532,6 +554,31 @@ __device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool i
   }
 }
 
+// One gather candidate: the record at slot r, which reaches p at offset
+// (oz, oy, ox) from its arrival point.
+template <int NDIM>
+__device__ __forceinline__ void cand_acc(const Rec<NDIM>& rec, int r, const vf4& a, float wx, float wy, float wz,
+                                         float& accI, float& accZ) {
+  (void)wz;
+  if (NDIM == 2) {
+    const float w = wx * wy;
+    accI = fmaf(w, a[2], accI);
+    accZ = fmaf(w, a[3], accZ);
+  } else {
+    const float w = wx * wy * wz;
+    accI = fmaf(w, a[3], accI);
+    accZ = fmaf(w, rec.zb[r], accZ);
+  }
+}
+
+template <int NDIM, int OZ, int OY, int OX>
+__device__ __forceinline__ void cand3(const Rec<NDIM>& rec, int rp, float& accI, float& accZ) {
+  constexpr int QX = Blk<NDIM>::X + 2 * Blk<NDIM>::HS, QY = Blk<NDIM>::Y + 2 * Blk<NDIM>::HS;
+  const int r = rp - (OZ * QY + OY) * QX - OX;  // q = p - o
+  const vf4 a = rec.v[r];
+  cand_acc<NDIM>(rec, r, a, tap3<OX>(a[0]), tap3<OY>(a[1]), NDIM == 3 ? tap3<OZ>(a[2]) : 1.f, accI, accZ);
+}
+
 template <int NDIM>
 __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__ pd, const Tile* __restrict__ tla,
                                                      const float* __restrict__ Vg, const float* __restrict__ stg,
@@ -545,11 +592,10 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   constexpr int NQ = ADJ_NQ<NDIM>();
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int ZH = NDIM == 3 ? HS : 0;
-  constexpr int COFF = 2 * HS;  // cell coordinates relative to P, shifted to be >= 0
-  __shared__ int rcell[NQ];
-  __shared__ float rf[NDIM][NQ];
-  __shared__ float rib[NQ], rzb[NQ];
+  __shared__ vf4 rvec[NQ];
+  __shared__ float rzb[NDIM == 3 ? NQ : 1];
   __shared__ float dbar[DX * DY * DZ];
+  const Rec<NDIM> rec{rvec, rzb};
   const Tile tl = tla[xcd_tile(gridDim.x)];
   const PairDev& P = pd[tl.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -577,12 +623,13 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
 #pragma unroll
     for (int c = 0; c < NDIM; ++c) vq[k][c] = 0.f;
     if (x0 + lx < nx && y0 + ly < ny && z0 + lz < nz)
-      adj_point<NDIM>(lx, ly, lz, r, true, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ,
-                      rcell, rf, rib, rzb, dbar, vq[k]);
+      adj_point<NDIM>(lx, ly, lz, r, true, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ, rec,
+                      dbar, vq[k]);
     else
-      rcell[r] = -1;
+      rec.clear(r);
   }
-  // phase 1b: the halo points around P (records and div_bar only)
+  // phase 1b: the halo points around P (records and div_bar only); slots of
+  // points outside the image or beyond P +- H hold zero cotangents
   const int hq = gmode ? H : 1;
   for (int li = threadIdx.x; li < NQ; li += NT) {
     const int lx = li % QX - HS, ly = (li / QX) % QY - HS, lz = NDIM == 3 ? li / (QX * QY) - HS : 0;
@@ -593,12 +640,12 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
                        (NDIM == 2 || (lz >= -hq && lz < PZ + hq)) && qx >= 0 && qx < nx && qy >= 0 &&
                        qy < ny && qz >= 0 && qz < nz;
     if (!visit) {
-      rcell[li] = -1;
+      rec.clear(li);
       continue;
     }
     float dummy[NDIM];
-    adj_point<NDIM>(lx, ly, lz, li, false, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ,
-                    rcell, rf, rib, rzb, dbar, dummy);
+    adj_point<NDIM>(lx, ly, lz, li, false, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ, rec,
+                    dbar, dummy);
   }
   __syncthreads();
 
@@ -614,28 +661,43 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
     gst(VB, (NDIM - 1) * N + idx, vq[k][NDIM - 1] + diffT_lds(dbar, b, qx, nx, 1));
     gst(VB, (NDIM - 2) * N + idx, vq[k][NDIM - 2] + diffT_lds(dbar, b, qy, ny, DX));
     if (NDIM == 3) gst(VB, idx, vq[k][0] + diffT_lds(dbar, b, qz, nz, DX * DY));
-    if (gmode) {
-      // Interp^T at p: sum over candidate arrival points q = p + (oz, oy, ox)
-      float accI = 0.f, accZ = 0.f;
+    if (!gmode) continue;
+    // Interp^T at p: sum over the arrival points q = p - o, |o| <= H per axis
+    const int rp = ((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS);
+    float accI = 0.f, accZ = 0.f;
+    if (H == 1) {
+      // fixed 3^d stencil, fixed order
+      if (NDIM == 3) {
+        cand3<NDIM, -1, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, -1, -1, 0>(rec, rp, accI, accZ);
+        cand3<NDIM, -1, -1, 1>(rec, rp, accI, accZ); cand3<NDIM, -1, 0, -1>(rec, rp, accI, accZ);
+        cand3<NDIM, -1, 0, 0>(rec, rp, accI, accZ);  cand3<NDIM, -1, 0, 1>(rec, rp, accI, accZ);
+        cand3<NDIM, -1, 1, -1>(rec, rp, accI, accZ); cand3<NDIM, -1, 1, 0>(rec, rp, accI, accZ);
+        cand3<NDIM, -1, 1, 1>(rec, rp, accI, accZ);
+        cand3<NDIM, 1, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, 1, -1, 0>(rec, rp, accI, accZ);
+        cand3<NDIM, 1, -1, 1>(rec, rp, accI, accZ);  cand3<NDIM, 1, 0, -1>(rec, rp, accI, accZ);
+        cand3<NDIM, 1, 0, 0>(rec, rp, accI, accZ);   cand3<NDIM, 1, 0, 1>(rec, rp, accI, accZ);
+        cand3<NDIM, 1, 1, -1>(rec, rp, accI, accZ);  cand3<NDIM, 1, 1, 0>(rec, rp, accI, accZ);
+        cand3<NDIM, 1, 1, 1>(rec, rp, accI, accZ);
+      }
+      cand3<NDIM, 0, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, 0, -1, 0>(rec, rp, accI, accZ);
+      cand3<NDIM, 0, -1, 1>(rec, rp, accI, accZ);  cand3<NDIM, 0, 0, -1>(rec, rp, accI, accZ);
+      cand3<NDIM, 0, 0, 0>(rec, rp, accI, accZ);   cand3<NDIM, 0, 0, 1>(rec, rp, accI, accZ);
+      cand3<NDIM, 0, 1, -1>(rec, rp, accI, accZ);  cand3<NDIM, 0, 1, 0>(rec, rp, accI, accZ);
+      cand3<NDIM, 0, 1, 1>(rec, rp, accI, accZ);
+    } else {
+      // general bound (2-D, 1 <= D < HS): hat weights over (2H + 1)^d offsets
       const int hz = NDIM == 3 ? H : 0;
       for (int oz = -hz; oz <= hz; ++oz)
         for (int oy = -H; oy <= H; ++oy)
           for (int ox = -H; ox <= H; ++ox) {
-            const int r = ((lz + oz + ZH) * QY + (ly + oy + HS)) * QX + (lx + ox + HS);
-            const int code = rcell[r];
-            if (code < 0) continue;
-            const int bx = lx + COFF - (code & 0xff);
-            const int by = ly + COFF - ((code >> 8) & 0xff);
-            const int bz = NDIM == 3 ? lz + COFF - ((code >> 16) & 0xff) : 0;
-            if ((unsigned)bx > 1u || (unsigned)by > 1u || (unsigned)bz > 1u) continue;
-            float w = (bx ? rf[NDIM - 1][r] : 1.f - rf[NDIM - 1][r]) * (by ? rf[NDIM - 2][r] : 1.f - rf[NDIM - 2][r]);
-            if (NDIM == 3) w *= bz ? rf[0][r] : 1.f - rf[0][r];
-            accI = fmaf(w, rib[r], accI);
-            accZ = fmaf(w, rzb[r], accZ);
+            const int r = rp - (oz * QY + oy) * QX - ox;
+            const vf4 a = rec.v[r];
+            cand_acc<NDIM>(rec, r, a, hat(a[0] - (float)ox), hat(a[1] - (float)oy),
+                           NDIM == 3 ? hat(a[2] - (float)oz) : 1.f, accI, accZ);
           }
-      gst(SI, idx, accI);
-      gst(SZ, idx, accZ);
     }
+    gst(SI, idx, accI);
+    gst(SZ, idx, accZ);
   }
 }
 
