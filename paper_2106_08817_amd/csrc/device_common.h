@@ -79,17 +79,12 @@ __device__ __forceinline__ Axis foot_axis(int q, float d, int n) {
   const float kf = floorf(d);
   const float fl = d - kf;            // in [0, 1]; may round to 1 for tiny negative d
   const int yb = q + (int)kf;
+  const bool lo = yb < 0, hi = yb >= n - 1;
+  const bool edge = (yb == 0 && fl == 0.f) || (yb == n - 2 && fl >= 1.f);
   Axis a;
-  if (yb < 0) {
-    a.i = 0; a.f = 0.f; a.live = 0.f;
-  } else if (yb >= n - 1) {
-    a.i = n - 2; a.f = 1.f; a.live = 0.f;
-  } else {
-    a.i = yb; a.f = fl;
-    const bool at_lo = (yb == 0) && (fl == 0.f);
-    const bool at_hi = (yb == n - 2) && (fl >= 1.f);
-    a.live = (at_lo || at_hi) ? 0.f : 1.f;
-  }
+  a.i = lo ? 0 : (hi ? n - 2 : yb);
+  a.f = lo ? 0.f : (hi ? 1.f : fl);
+  a.live = (lo || hi || edge) ? 0.f : 1.f;
   return a;
 }
 

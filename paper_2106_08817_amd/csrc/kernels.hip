@@ -66,16 +66,23 @@ __global__ __launch_bounds__(NT) void k_init(const PairDev* __restrict__ pd, con
   float* __restrict__ I = st + 2 * P.off;
   const float* __restrict__ S = P.S;
   const float* __restrict__ Q = P.p0;
+  unsigned idx[B::PPT];
+  bool inside[B::PPT];
+  float sv[B::PPT], qv[B::PPT];
 #pragma unroll
   for (int k = 0; k < B::PPT; ++k) {
     int lx, ly, lz;
     B::local(threadIdx.x, k, lx, ly, lz);
-    const int x = t.a + lx, y = t.b + ly, z = t.c + lz;
-    if (x < nx && y < ny && z < nz) {
-      const unsigned idx = (unsigned)((z * ny + y) * nx + x);
-      gst(I, idx, gld(S, idx));
-      gst(I, N + idx, gld(Q, idx));
-    }
+    inside[k] = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
+    idx[k] = (unsigned)((min(t.c + lz, nz - 1) * ny + min(t.b + ly, ny - 1)) * nx + min(t.a + lx, nx - 1));
+    sv[k] = gld(S, idx[k]);
+    qv[k] = gld(Q, idx[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < B::PPT; ++k) {
+    if (!inside[k]) continue;
+    gst(I, idx[k], sv[k]);
+    gst(I, N + idx[k], qv[k]);
   }
 }
 
@@ -102,76 +109,55 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   const int row0 = t.a, nrows = t.b;
   const int plane = nrows * L;
 
-  // fill: one wave per row, lanes along the row, four columns per lane in
-  // flight (clamped loads, zero outside the row)
+  // fill: the tile is cut into segments of 64 columns of one row; wave w
+  // takes segments w, w + 4, ... and issues the loads of XSEG of them at once
+  // (clamped loads, zero outside the row)
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  if (GRADMUL) {
-    const float* __restrict__ I = src + 2 * P.off;
-    const float* __restrict__ Z = I + N;
-    for (int rl = wv; rl < nrows; rl += NT / 64) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nch = (L + 63) >> 6;
+  const int nseg = nrows * nch;
+  const float* __restrict__ I = src + (GRADMUL ? 2 : NDIM) * P.off;
+  const float* __restrict__ Z = I + N;
+  for (int sb = 0; sb < nseg; sb += XSEG * (NT / 64)) {
+    float m[XSEG][NDIM];
+    int lcol[XSEG];
+#pragma unroll
+    for (int u = 0; u < XSEG; ++u) {
+      const int sg = min(sb + wv + u * (NT / 64), nseg - 1);  // wave-uniform
+      const int rl = sg / nch;
+      const int col = (sg - rl * nch) * 64 + lane;
+      lcol[u] = (sb + wv + u * (NT / 64) < nseg && col < L) ? rl * L + col : -1;
       const int row = row0 + rl;
-      const int y = row % ny;
-      const unsigned rbase = (unsigned)(row * nx);
-      const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
-      unsigned zu = 0, zd = 0;
-      if (NDIM == 3) {
-        const int z = row / ny;
-        zu = (unsigned)up(z, nz, ny * nx);
-        zd = (unsigned)dn(z, ny * nx);
-      }
-      float* Lrow = lds + rl * L;
-      for (int c0 = 0; c0 < L; c0 += 4 * 64) {
-        float m[4][NDIM];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int x = c0 + u * 64 + lane - r;
-          const int xc = clampi(x, 0, nx - 1);
-          const unsigned idx = rbase + (unsigned)xc;
-          const float zq = 0.5f * gld(Z, idx);
-          const float gx = gld(I, idx + (xc + 1 < nx ? 1u : 0u)) - gld(I, idx - (xc > 0 ? 1u : 0u));
-          const float gy = gld(I, idx + yu) - gld(I, idx - yd);
-          const bool in = x >= 0 && x < nx;
-          m[u][NDIM - 1] = in ? zq * gx : 0.f;
-          m[u][NDIM - 2] = in ? zq * gy : 0.f;
-          if (NDIM == 3) m[u][0] = in ? zq * (gld(I, idx + zu) - gld(I, idx - zd)) : 0.f;
+      const int x = col - r;
+      const int xc = clampi(x, 0, nx - 1);
+      const unsigned idx = (unsigned)(row * nx + xc);
+      const bool in = x >= 0 && x < nx;
+      if (GRADMUL) {
+        const int y = row % ny;
+        const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
+        const float zq = 0.5f * gld(Z, idx);
+        const float gx = gld(I, idx + (xc + 1 < nx ? 1u : 0u)) - gld(I, idx - (xc > 0 ? 1u : 0u));
+        const float gy = gld(I, idx + yu) - gld(I, idx - yd);
+        m[u][NDIM - 1] = in ? zq * gx : 0.f;
+        m[u][NDIM - 2] = in ? zq * gy : 0.f;
+        if (NDIM == 3) {
+          const int z = row / ny;
+          const unsigned zu = (unsigned)up(z, nz, ny * nx), zd = (unsigned)dn(z, ny * nx);
+          m[u][0] = in ? zq * (gld(I, idx + zu) - gld(I, idx - zd)) : 0.f;
         }
+      } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int col = c0 + u * 64 + lane;
-          if (col < L) {
-#pragma unroll
-            for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = m[u][c];
-          }
+        for (int c = 0; c < NDIM; ++c) {
+          const float v = gld(I, c * N + idx);
+          m[u][c] = in ? v : 0.f;
         }
       }
     }
-  } else {
-    const float* __restrict__ F = src + NDIM * P.off;
-    for (int rl = wv; rl < nrows; rl += NT / 64) {
-      const unsigned rbase = (unsigned)((row0 + rl) * nx);
-      float* Lrow = lds + rl * L;
-      for (int c0 = 0; c0 < L; c0 += 4 * 64) {
-        float m[4][NDIM];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int x = c0 + u * 64 + lane - r;
-          const unsigned idx = rbase + (unsigned)clampi(x, 0, nx - 1);
-          const bool in = x >= 0 && x < nx;
+    for (int u = 0; u < XSEG; ++u) {
+      if (lcol[u] >= 0) {
 #pragma unroll
-          for (int c = 0; c < NDIM; ++c) {
-            const float v = gld(F, c * N + idx);
-            m[u][c] = in ? v : 0.f;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int col = c0 + u * 64 + lane;
-          if (col < L) {
-#pragma unroll
-            for (int c = 0; c < NDIM; ++c) Lrow[c * plane + col] = m[u][c];
-          }
-        }
+        for (int c = 0; c < NDIM; ++c) lds[c * plane + lcol[u]] = m[u][c];
       }
     }
   }
@@ -247,17 +233,17 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const unsigned base = (unsigned)t.b * so + (unsigned)min(x, nx - 1);
   const float* __restrict__ Fc = src + NDIM * P.off + c * N;
 
-  // fill: clamped loads, eight rows per thread in flight
-  for (int j0 = wv; j0 < rows; j0 += 8 * (NT / 64)) {
-    float v[8];
+  // fill: clamped loads, SFILL rows per thread in flight
+  for (int j0 = wv; j0 < rows; j0 += SFILL * (NT / 64)) {
+    float v[SFILL];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < SFILL; ++u) {
       const int s = s0 - r + j0 + u * (NT / 64);
       const float f = gld(Fc, base + (unsigned)clampi(s, 0, ns - 1) * ss);
       v[u] = (xin && s >= 0 && s < ns) ? f : 0.f;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < SFILL; ++u) {
       const int j = j0 + u * (NT / 64);
       if (j < rows) lds[j * 64 + lane] = v[u];
     }
@@ -303,12 +289,58 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
 // ----------------------------------------------------------------------------
 // semi-Lagrangian advection (forward step)
 // ----------------------------------------------------------------------------
+//
+// The voxels of a thread are handled in batches of GS: all loads of a batch
+// (velocity at q and its axis neighbours) are issued together, then all feet
+// are formed and all corner gathers issued together, so each batch costs two
+// memory round trips rather than two per voxel.
+
+// velocity at q (channel order) and its clamped axis neighbours for div v
+template <int NDIM>
+__device__ __forceinline__ void load_v_div(const float* __restrict__ V, unsigned N, unsigned idx, int qx, int qy,
+                                           int qz, int nx, int ny, int nz, float v[NDIM], float vn[2 * NDIM]) {
+  const unsigned sxy = (unsigned)(nx * ny);
+  const float* Vx = V + (NDIM - 1) * N;
+  const float* Vy = V + (NDIM - 2) * N;
+#pragma unroll
+  for (int c = 0; c < NDIM; ++c) v[c] = gld(V, c * N + idx);
+  vn[0] = gld(Vx, idx + (unsigned)up(qx, nx, 1));
+  vn[1] = gld(Vx, idx - (unsigned)dn(qx, 1));
+  vn[2] = gld(Vy, idx + (unsigned)up(qy, ny, nx));
+  vn[3] = gld(Vy, idx - (unsigned)dn(qy, nx));
+  if (NDIM == 3) {
+    vn[4] = gld(V, idx + (unsigned)up(qz, nz, sxy));
+    vn[5] = gld(V, idx - (unsigned)dn(qz, sxy));
+  }
+}
+
+template <int NDIM>
+__device__ __forceinline__ float div_of(const float vn[2 * NDIM]) {
+  float d = 0.5f * (vn[0] - vn[1]);
+  d += 0.5f * (vn[2] - vn[3]);
+  if (NDIM == 3) d += 0.5f * (vn[4] - vn[5]);
+  return d;
+}
+
+// Multilinear combination of the 2^d corner values (corner k: bit 0 = x,
+// bit 1 = y, bit 2 = z) with fractions f = (fz, fy, fx).
+template <int NDIM>
+__device__ __forceinline__ float mlerp(const float* c, const float f[3]) {
+  const float wx0 = 1.f - f[2], wx1 = f[2], wy0 = 1.f - f[1], wy1 = f[1];
+  const float a = wy0 * (wx0 * c[0] + wx1 * c[1]) + wy1 * (wx0 * c[2] + wx1 * c[3]);
+  if (NDIM == 2) return a;
+  const float b = wy0 * (wx0 * c[4] + wx1 * c[5]) + wy1 * (wx0 * c[6] + wx1 * c[7]);
+  return (1.f - f[0]) * a + f[0] * b;
+}
 
 template <int NDIM>
 __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                const float* __restrict__ Vg, const float* __restrict__ stg,
                                                float* __restrict__ stog, AdvectArgs A) {
   using B = Blk<NDIM>;
+  constexpr int GS = NDIM == 2 ? ADV_BATCH2 : ADV_BATCH3;
+  constexpr int NC = NDIM == 3 ? 8 : 4;
+  static_assert(B::PPT % GS == 0, "batch must divide the voxels per thread");
   __shared__ float sh[NT / 64];
   const int tix = xcd_tile(gridDim.x);
   const Tile t = tl[tix];
@@ -323,80 +355,102 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
   float* __restrict__ Io = stog ? stog + 2 * P.off : nullptr;
   float reg = 0.f, ssd = 0.f, dm = 0.f;
 #pragma unroll
-  for (int k = 0; k < B::PPT; ++k) {
-    int lx, ly, lz;
-    B::local(threadIdx.x, k, lx, ly, lz);
-    const bool inside = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
-    const int xq = min(t.a + lx, nx - 1), yq = min(t.b + ly, ny - 1), zq = min(t.c + lz, nz - 1);
-    const unsigned idx = (unsigned)((zq * ny + yq) * nx + xq);
-    float v[NDIM];
+  for (int k0 = 0; k0 < B::PPT; k0 += GS) {
+    int qx[GS], qy[GS], qz[GS];
+    unsigned idx[GS];
+    bool inside[GS];
+    float v[GS][NDIM], vn[GS][2 * NDIM];
 #pragma unroll
-    for (int c = 0; c < NDIM; ++c) v[c] = gld(V, c * N + idx);
-    // div v at q (clamped central differences)
-    const float* Vx = V + (NDIM - 1) * N;
-    const float* Vy = V + (NDIM - 2) * N;
-    float div = 0.5f * (gld(Vx, idx + (unsigned)up(xq, nx, 1)) - gld(Vx, idx - (unsigned)dn(xq, 1)));
-    div += 0.5f * (gld(Vy, idx + (unsigned)up(yq, ny, nx)) - gld(Vy, idx - (unsigned)dn(yq, nx)));
-    if (NDIM == 3) div += 0.5f * (gld(V, idx + (unsigned)up(zq, nz, sxy)) - gld(V, idx - (unsigned)dn(zq, sxy)));
-    const float dx = -dt * v[NDIM - 1], dy = -dt * v[NDIM - 2];
-    const Axis ax = foot_axis(xq, dx, nx);
-    const Axis ay = foot_axis(yq, dy, ny);
-    float dmq = fmaxf(fabsf(dx), fabsf(dy));
-    float Ih, zh;
-    if (NDIM == 2) {
-      const unsigned c00 = (unsigned)(ay.i * nx + ax.i);
-      const float wy0 = 1.f - ay.f, wy1 = ay.f, wx0 = 1.f - ax.f, wx1 = ax.f;
-      const unsigned c10 = c00 + (unsigned)nx;
-      Ih = wy0 * (wx0 * gld(I, c00) + wx1 * gld(I, c00 + 1)) + wy1 * (wx0 * gld(I, c10) + wx1 * gld(I, c10 + 1));
-      zh = wy0 * (wx0 * gld(Z, c00) + wx1 * gld(Z, c00 + 1)) + wy1 * (wx0 * gld(Z, c10) + wx1 * gld(Z, c10 + 1));
-    } else {
-      const float dz = -dt * v[0];
-      dmq = fmaxf(dmq, fabsf(dz));
-      const Axis az = foot_axis(zq, dz, nz);
-      const unsigned c000 = (unsigned)(az.i * (int)sxy + ay.i * nx + ax.i);
-      const float wz0 = 1.f - az.f, wz1 = az.f, wy0 = 1.f - ay.f, wy1 = ay.f, wx0 = 1.f - ax.f, wx1 = ax.f;
-      const unsigned c010 = c000 + nx, c100 = c000 + sxy, c110 = c100 + nx;
-      Ih = wz0 * (wy0 * (wx0 * gld(I, c000) + wx1 * gld(I, c000 + 1)) + wy1 * (wx0 * gld(I, c010) + wx1 * gld(I, c010 + 1))) +
-           wz1 * (wy0 * (wx0 * gld(I, c100) + wx1 * gld(I, c100 + 1)) + wy1 * (wx0 * gld(I, c110) + wx1 * gld(I, c110 + 1)));
-      zh = wz0 * (wy0 * (wx0 * gld(Z, c000) + wx1 * gld(Z, c000 + 1)) + wy1 * (wx0 * gld(Z, c010) + wx1 * gld(Z, c010 + 1))) +
-           wz1 * (wy0 * (wx0 * gld(Z, c100) + wx1 * gld(Z, c100 + 1)) + wy1 * (wx0 * gld(Z, c110) + wx1 * gld(Z, c110 + 1)));
+    for (int g = 0; g < GS; ++g) {
+      int lx, ly, lz;
+      B::local(threadIdx.x, k0 + g, lx, ly, lz);
+      inside[g] = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
+      qx[g] = min(t.a + lx, nx - 1); qy[g] = min(t.b + ly, ny - 1); qz[g] = min(t.c + lz, nz - 1);
+      idx[g] = (unsigned)((qz[g] * ny + qy[g]) * nx + qx[g]);
+      load_v_div<NDIM>(V, N, idx[g], qx[g], qy[g], qz[g], nx, ny, nz, v[g], vn[g]);
     }
-    const float In = fmaf(rdt, zh, Ih);
-    const float zn = zh * (1.f - dt * div);
-    if (!inside) continue;
-    dm = fmaxf(dm, dmq);
-    if (Io) {
-      gst(Io, idx, In);
-      gst(Io, N + idx, zn);
+    float iv[GS][NC], zv[GS][NC], fr[GS][3], dmq[GS];
+#pragma unroll
+    for (int g = 0; g < GS; ++g) {
+      const float dx = -dt * v[g][NDIM - 1], dy = -dt * v[g][NDIM - 2];
+      const Axis ax = foot_axis(qx[g], dx, nx);
+      const Axis ay = foot_axis(qy[g], dy, ny);
+      dmq[g] = fmaxf(fabsf(dx), fabsf(dy));
+      int zi = 0;
+      fr[g][0] = 0.f;
+      if (NDIM == 3) {
+        const float dz = -dt * v[g][0];
+        const Axis az = foot_axis(qz[g], dz, nz);
+        dmq[g] = fmaxf(dmq[g], fabsf(dz));
+        zi = az.i;
+        fr[g][0] = az.f;
+      }
+      fr[g][1] = ay.f;
+      fr[g][2] = ax.f;
+      const unsigned c0 = (unsigned)(zi * (int)sxy + ay.i * nx + ax.i);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const unsigned gi = c0 + (unsigned)(j >> 2) * sxy + (unsigned)(((j >> 1) & 1) * nx + (j & 1));
+        iv[g][j] = gld(I, gi);
+        zv[g][j] = gld(Z, gi);
+      }
+    }
+    float In[GS], zn[GS];
+#pragma unroll
+    for (int g = 0; g < GS; ++g) {
+      const float Ih = mlerp<NDIM>(iv[g], fr[g]);
+      const float zh = mlerp<NDIM>(zv[g], fr[g]);
+      In[g] = fmaf(rdt, zh, Ih);
+      zn[g] = zh * (1.f - dt * div_of<NDIM>(vn[g]));
+    }
+#pragma unroll
+    for (int g = 0; g < GS; ++g) {
+      if (!inside[g]) continue;
+      dm = fmaxf(dm, dmq[g]);
+      if (Io) {
+        gst(Io, idx[g], In[g]);
+        gst(Io, N + idx[g], zn[g]);
+      }
     }
     if (A.red_reg) {
       // -<m_0, v_0> + rho |p0|^2 at q, with m_c = z D_c I
-      const float zq0 = gld(Z, idx);
-      float g[NDIM];
-      g[NDIM - 1] = 0.5f * (gld(I, idx + (unsigned)up(xq, nx, 1)) - gld(I, idx - (unsigned)dn(xq, 1)));
-      g[NDIM - 2] = 0.5f * (gld(I, idx + (unsigned)up(yq, ny, nx)) - gld(I, idx - (unsigned)dn(yq, nx)));
-      if (NDIM == 3) g[0] = 0.5f * (gld(I, idx + (unsigned)up(zq, nz, sxy)) - gld(I, idx - (unsigned)dn(zq, sxy)));
-      float mv = 0.f;
 #pragma unroll
-      for (int c = 0; c < NDIM; ++c) mv = fmaf(zq0 * g[c], v[c], mv);
-      reg += P.rho * zq0 * zq0 - mv;
+      for (int g = 0; g < GS; ++g) {
+        if (!inside[g]) continue;
+        const unsigned i0 = idx[g];
+        const float zq0 = gld(Z, i0);
+        float gr[NDIM];
+        gr[NDIM - 1] = 0.5f * (gld(I, i0 + (unsigned)up(qx[g], nx, 1)) - gld(I, i0 - (unsigned)dn(qx[g], 1)));
+        gr[NDIM - 2] = 0.5f * (gld(I, i0 + (unsigned)up(qy[g], ny, nx)) - gld(I, i0 - (unsigned)dn(qy[g], nx)));
+        if (NDIM == 3)
+          gr[0] = 0.5f * (gld(I, i0 + (unsigned)up(qz[g], nz, sxy)) - gld(I, i0 - (unsigned)dn(qz[g], sxy)));
+        float mv = 0.f;
+#pragma unroll
+        for (int c = 0; c < NDIM; ++c) mv = fmaf(zq0 * gr[c], v[g][c], mv);
+        reg += P.rho * zq0 * zq0 - mv;
+      }
     }
     if (A.last) {
-      if (P.outI) P.outI[idx] = In;
-      if (P.outZ) P.outZ[idx] = zn;
-      if (P.J) {
-        const float R = In - P.J[idx];
-        ssd = fmaf(0.5f * R, R, ssd);
-        if (A.ab_out) {
-          float* AB = A.ab_out + 2 * P.off;
-          AB[idx] = R;
-          AB[N + idx] = 0.f;
+#pragma unroll
+      for (int g = 0; g < GS; ++g) {
+        if (!inside[g]) continue;
+        const unsigned i0 = idx[g];
+        if (P.outI) P.outI[i0] = In[g];
+        if (P.outZ) P.outZ[i0] = zn[g];
+        if (P.J) {
+          const float R = In[g] - P.J[i0];
+          ssd = fmaf(0.5f * R, R, ssd);
+          if (A.ab_out) {
+            float* AB = A.ab_out + 2 * P.off;
+            AB[i0] = R;
+            AB[N + i0] = 0.f;
+          }
         }
-      }
-      if (A.sc_zero) {
-        float* SC = A.sc_zero + 2 * P.off;
-        SC[idx] = 0.f;
-        SC[N + idx] = 0.f;
+        if (A.sc_zero) {
+          float* SC = A.sc_zero + 2 * P.off;
+          SC[i0] = 0.f;
+          SC[N + i0] = 0.f;
+        }
       }
     }
   }
@@ -471,86 +525,145 @@ __device__ __forceinline__ float tap3(float e) {
 
 __device__ __forceinline__ float hat(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
 
-// Phase-1 work for one arrival point (local coordinates l* relative to P,
-// record slot li): its record, div_bar (on P +- 1), the global scatter
-// (fallback mode) and, for q in P, the foot-point part of vbar (into vq).
+// Slot of the j-th point of the ring P +- HS minus P (ring order: the HS
+// full planes / rows on each side, then the sides of the remaining ones), as
+// local coordinates relative to the tile origin.
 template <int NDIM>
-__device__ __forceinline__ void adj_point(int lx, int ly, int lz, int li, bool inP, bool gmode, int x0, int y0,
-                                          int z0, int nx, int ny, int nz, unsigned N, float dt, float rdt,
-                                          const float* __restrict__ V, const float* __restrict__ I,
-                                          const float* __restrict__ Z, const float* __restrict__ AB,
-                                          float* __restrict__ SI, float* __restrict__ SZ, const Rec<NDIM>& rec,
-                                          float* dbar, float vq[NDIM]) {
+__host__ __device__ __forceinline__ void ring_point(int j, int& lx, int& ly, int& lz) {
+  using B = Blk<NDIM>;
+  constexpr int HS = B::HS, QX = B::X + 2 * HS, QY = B::Y + 2 * HS, QZ = B::Z + 2 * HS;
+  constexpr int R2 = QX * QY - B::X * B::Y;  // ring of one plane
+  int qzl = 0;
+  if (NDIM == 3) {
+    constexpr int FP = QX * QY;
+    if (j < 2 * HS * FP) {
+      const int pl = j / FP;
+      qzl = pl < HS ? pl : QZ - 2 * HS + pl;
+      j -= pl * FP;
+      ly = j / QX - HS;
+      lx = j % QX - HS;
+      lz = qzl - HS;
+      return;
+    }
+    j -= 2 * HS * FP;
+    qzl = HS + j / R2;
+    j %= R2;
+  }
+  constexpr int TOP = HS * QX;
+  int qyl, qxl;
+  if (j < 2 * TOP) {
+    const int rw = j / QX;
+    qyl = rw < HS ? rw : QY - 2 * HS + rw;
+    qxl = j % QX;
+  } else {
+    j -= 2 * TOP;
+    qyl = HS + j / (2 * HS);
+    const int c = j % (2 * HS);
+    qxl = c < HS ? c : B::X + c;
+  }
+  lx = qxl - HS;
+  ly = qyl - HS;
+  lz = NDIM == 3 ? qzl - HS : 0;
+}
+
+// Phase-1 work of the adjoint for a batch of G arrival points (local
+// coordinates l*, record slots li; act = the point is in the image and
+// within reach of P): its record, div_bar on P +- 1, the global scatter
+// (fallback mode) and, for OWN points (the thread's outputs), the foot-point
+// part of vbar. The loads of the whole batch are issued together in two
+// rounds (fields at q, then the corners of the feet).
+template <int NDIM, int G, bool OWN>
+__device__ __forceinline__ void adj_batch(const int (&lx)[G], const int (&ly)[G], const int (&lz)[G],
+                                          const int (&li)[G], const bool (&act)[G], const bool (&slot)[G],
+                                          bool gmode, int x0, int y0, int z0, int nx, int ny, int nz, unsigned N,
+                                          float dt, float rdt, const float* __restrict__ V,
+                                          const float* __restrict__ I, const float* __restrict__ Z,
+                                          const float* __restrict__ AB, float* __restrict__ SI,
+                                          float* __restrict__ SZ, const Rec<NDIM>& rec, float* dbar,
+                                          float (*vq)[NDIM]) {
   using B = Blk<NDIM>;
   constexpr int DX = B::X + 2, DY = B::Y + 2;
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int NC = NDIM == 3 ? 8 : 4;
   const unsigned sxy = (unsigned)(nx * ny);
-  const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
-  const bool inP1 = lx >= -1 && lx <= B::X && ly >= -1 && ly <= B::Y && (NDIM == 2 || (lz >= -1 && lz <= B::Z));
-  const unsigned idx = (unsigned)((qz * ny + qy) * nx + qx);
-  const float* Vx = V + (NDIM - 1) * N;
-  const float* Vy = V + (NDIM - 2) * N;
-  float div = 0.5f * (gld(Vx, idx + (unsigned)up(qx, nx, 1)) - gld(Vx, idx - (unsigned)dn(qx, 1)));
-  div += 0.5f * (gld(Vy, idx + (unsigned)up(qy, ny, nx)) - gld(Vy, idx - (unsigned)dn(qy, nx)));
-  if (NDIM == 3) div += 0.5f * (gld(V, idx + (unsigned)up(qz, nz, sxy)) - gld(V, idx - (unsigned)dn(qz, sxy)));
-  const float Ib = gld(AB, idx);
-  const float zb = gld(AB, N + idx);
-  const Axis ax = foot_axis(qx, -dt * gld(Vx, idx), nx);
-  const Axis ay = foot_axis(qy, -dt * gld(Vy, idx), ny);
-  Axis az;
-  if (NDIM == 3) {
-    az = foot_axis(qz, -dt * gld(V, idx), nz);
-  } else {
-    az.i = 0; az.f = 0.f; az.live = 0.f;
-  }
-  const float wz[2] = {1.f - az.f, az.f}, wy[2] = {1.f - ay.f, ay.f}, wx[2] = {1.f - ax.f, ax.f};
-  const unsigned c0 = (unsigned)(az.i * (int)sxy + ay.i * nx + ax.i);
-  float zv[NC], iv[NC];
+  int qx[G], qy[G], qz[G];
+  unsigned idx[G];
+  float v[G][NDIM], vn[G][2 * NDIM], ib[G], zb[G];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-    const unsigned g = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
-    zv[k] = gld(Z, g);
-    if (inP) iv[k] = gld(I, g);
+  for (int g = 0; g < G; ++g) {
+    qx[g] = clampi(x0 + lx[g], 0, nx - 1);
+    qy[g] = clampi(y0 + ly[g], 0, ny - 1);
+    qz[g] = clampi(z0 + lz[g], 0, nz - 1);
+    idx[g] = (unsigned)((qz[g] * ny + qy[g]) * nx + qx[g]);
+    load_v_div<NDIM>(V, N, idx[g], qx[g], qy[g], qz[g], nx, ny, nz, v[g], vn[g]);
+    ib[g] = gld(AB, idx[g]);
+    zb[g] = gld(AB, N + idx[g]);
   }
-  float zh = 0.f;
+  Axis ax[G], ay[G], az[G];
+  float zv[G][NC], iv[G][NC];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-    zh = fmaf((NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx], zv[k], zh);
-  }
-  const float zhb = fmaf(rdt, Ib, (1.f - dt * div) * zb);
-  if (inP1) dbar[((lz + ZO) * DY + (ly + 1)) * DX + (lx + 1)] = -dt * zh * zb;
-  if (gmode) {
-    rec.put(li, (float)(ax.i - qx) + ax.f, (float)(ay.i - qy) + ay.f, NDIM == 3 ? (float)(az.i - qz) + az.f : 0.f,
-            Ib, zhb);
-  } else if (inP) {
+  for (int g = 0; g < G; ++g) {
+    ax[g] = foot_axis(qx[g], -dt * v[g][NDIM - 1], nx);
+    ay[g] = foot_axis(qy[g], -dt * v[g][NDIM - 2], ny);
+    if (NDIM == 3) {
+      az[g] = foot_axis(qz[g], -dt * v[g][0], nz);
+    } else {
+      az[g].i = 0; az[g].f = 0.f; az[g].live = 0.f;
+    }
+    const unsigned c0 = (unsigned)(az[g].i * (int)sxy + ay[g].i * nx + ax[g].i);
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-      const float w = (NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx];
-      const unsigned g = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
-      unsafeAtomicAdd(SI + g, w * Ib);
-      unsafeAtomicAdd(SZ + g, w * zhb);
+      const unsigned gi = c0 + (unsigned)(k >> 2) * sxy + (unsigned)(((k >> 1) & 1) * nx + (k & 1));
+      zv[g][k] = gld(Z, gi);
+      if (OWN) iv[g][k] = gld(I, gi);
     }
   }
-  if (inP) {
-    float gI[3] = {0.f, 0.f, 0.f}, gZ[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
-      const float wzz = NDIM == 3 ? wz[bz] : 1.f;
-      const float ddz = (bz ? 1.f : -1.f) * wy[by] * wx[bx];
-      const float ddy = (by ? 1.f : -1.f) * wzz * wx[bx];
-      const float ddx = (bx ? 1.f : -1.f) * wzz * wy[by];
-      gI[0] = fmaf(ddz, iv[k], gI[0]); gZ[0] = fmaf(ddz, zv[k], gZ[0]);
-      gI[1] = fmaf(ddy, iv[k], gI[1]); gZ[1] = fmaf(ddy, zv[k], gZ[1]);
-      gI[2] = fmaf(ddx, iv[k], gI[2]); gZ[2] = fmaf(ddx, zv[k], gZ[2]);
+  for (int g = 0; g < G; ++g) {
+    const float fr[3] = {az[g].f, ay[g].f, ax[g].f};
+    const float zh = mlerp<NDIM>(zv[g], fr);
+    const float zhb = fmaf(rdt, ib[g], (1.f - dt * div_of<NDIM>(vn[g])) * zb[g]);
+    const bool inP1 = lx[g] >= -1 && lx[g] <= B::X && ly[g] >= -1 && ly[g] <= B::Y &&
+                      (NDIM == 2 || (lz[g] >= -1 && lz[g] <= B::Z));
+    if (act[g] && inP1) dbar[((lz[g] + ZO) * DY + (ly[g] + 1)) * DX + (lx[g] + 1)] = -dt * zh * zb[g];
+    if (gmode) {
+      if (act[g])
+        rec.put(li[g], (float)(ax[g].i - qx[g]) + ax[g].f, (float)(ay[g].i - qy[g]) + ay[g].f,
+                NDIM == 3 ? (float)(az[g].i - qz[g]) + az[g].f : 0.f, ib[g], zhb);
+      else if (slot[g])
+        rec.clear(li[g]);
+    } else if (OWN && act[g]) {
+      const float wz[2] = {1.f - az[g].f, az[g].f}, wy[2] = {1.f - ay[g].f, ay[g].f};
+      const float wx[2] = {1.f - ax[g].f, ax[g].f};
+      const unsigned c0 = (unsigned)(az[g].i * (int)sxy + ay[g].i * nx + ax[g].i);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
+        const float w = (NDIM == 3 ? wz[bz] : 1.f) * wy[by] * wx[bx];
+        const unsigned gi = c0 + (unsigned)bz * sxy + (unsigned)(by * nx + bx);
+        unsafeAtomicAdd(SI + gi, w * ib[g]);
+        unsafeAtomicAdd(SZ + gi, w * zhb);
+      }
     }
-    vq[NDIM - 1] = -dt * ax.live * fmaf(Ib, gI[2], zhb * gZ[2]);
-    vq[NDIM - 2] = -dt * ay.live * fmaf(Ib, gI[1], zhb * gZ[1]);
-    if (NDIM == 3) vq[0] = -dt * az.live * fmaf(Ib, gI[0], zhb * gZ[0]);
+    if (OWN) {
+      const float wz[2] = {1.f - az[g].f, az[g].f}, wy[2] = {1.f - ay[g].f, ay[g].f};
+      const float wx[2] = {1.f - ax[g].f, ax[g].f};
+      float gI[3] = {0.f, 0.f, 0.f}, gZ[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int bz = k >> 2, by = (k >> 1) & 1, bx = k & 1;
+        const float wzz = NDIM == 3 ? wz[bz] : 1.f;
+        const float ddz = (bz ? 1.f : -1.f) * wy[by] * wx[bx];
+        const float ddy = (by ? 1.f : -1.f) * wzz * wx[bx];
+        const float ddx = (bx ? 1.f : -1.f) * wzz * wy[by];
+        gI[0] = fmaf(ddz, iv[g][k], gI[0]); gZ[0] = fmaf(ddz, zv[g][k], gZ[0]);
+        gI[1] = fmaf(ddy, iv[g][k], gI[1]); gZ[1] = fmaf(ddy, zv[g][k], gZ[1]);
+        gI[2] = fmaf(ddx, iv[g][k], gI[2]); gZ[2] = fmaf(ddx, zv[g][k], gZ[2]);
+      }
+      vq[g][NDIM - 1] = -dt * ax[g].live * fmaf(ib[g], gI[2], zhb * gZ[2]);
+      vq[g][NDIM - 2] = -dt * ay[g].live * fmaf(ib[g], gI[1], zhb * gZ[1]);
+      if (NDIM == 3) vq[g][0] = -dt * az[g].live * fmaf(ib[g], gI[0], zhb * gZ[0]);
+    }
   }
 }
 
@@ -590,8 +703,13 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   constexpr int DX = PX + 2, DY = PY + 2, DZ = NDIM == 3 ? PZ + 2 : 1;
   constexpr int QX = PX + 2 * HS, QY = PY + 2 * HS;
   constexpr int NQ = ADJ_NQ<NDIM>();
+  constexpr int NR = NQ - B::NP;  // ring slots
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int ZH = NDIM == 3 ? HS : 0;
+  constexpr int GS = NDIM == 2 ? ADJ_BATCH2 : ADJ_BATCH3;  // own points per batch
+  constexpr int GR = NDIM == 2 ? ADJ_RING_BATCH2 : ADJ_RING_BATCH3;  // ring points per batch
+  constexpr int NRB = (NR + GR * NT - 1) / (GR * NT);   // ring batches
+  static_assert(PPT % GS == 0, "batch must divide the voxels per thread");
   __shared__ vf4 rvec[NQ];
   __shared__ float rzb[NDIM == 3 ? NQ : 1];
   __shared__ float dbar[DX * DY * DZ];
@@ -616,36 +734,39 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   // phase 1a: the outputs of this thread (same mapping as phase 2)
   float vq[PPT][NDIM];
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    int lx, ly, lz;
-    B::local(threadIdx.x, k, lx, ly, lz);
-    const int r = ((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS);
+  for (int k0 = 0; k0 < PPT; k0 += GS) {
+    int lx[GS], ly[GS], lz[GS], li[GS];
+    bool act[GS], slot[GS];
 #pragma unroll
-    for (int c = 0; c < NDIM; ++c) vq[k][c] = 0.f;
-    if (x0 + lx < nx && y0 + ly < ny && z0 + lz < nz)
-      adj_point<NDIM>(lx, ly, lz, r, true, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ, rec,
-                      dbar, vq[k]);
-    else
-      rec.clear(r);
-  }
-  // phase 1b: the halo points around P (records and div_bar only); slots of
-  // points outside the image or beyond P +- H hold zero cotangents
-  const int hq = gmode ? H : 1;
-  for (int li = threadIdx.x; li < NQ; li += NT) {
-    const int lx = li % QX - HS, ly = (li / QX) % QY - HS, lz = NDIM == 3 ? li / (QX * QY) - HS : 0;
-    const bool inP = lx >= 0 && lx < PX && ly >= 0 && ly < PY && lz >= 0 && lz < PZ;
-    if (inP) continue;
-    const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
-    const bool visit = lx >= -hq && lx < PX + hq && ly >= -hq && ly < PY + hq &&
-                       (NDIM == 2 || (lz >= -hq && lz < PZ + hq)) && qx >= 0 && qx < nx && qy >= 0 &&
-                       qy < ny && qz >= 0 && qz < nz;
-    if (!visit) {
-      rec.clear(li);
-      continue;
+    for (int g = 0; g < GS; ++g) {
+      B::local(threadIdx.x, k0 + g, lx[g], ly[g], lz[g]);
+      li[g] = ((lz[g] + ZH) * QY + (ly[g] + HS)) * QX + (lx[g] + HS);
+      act[g] = x0 + lx[g] < nx && y0 + ly[g] < ny && z0 + lz[g] < nz;
+      slot[g] = true;
     }
-    float dummy[NDIM];
-    adj_point<NDIM>(lx, ly, lz, li, false, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ, rec,
-                    dbar, dummy);
+    adj_batch<NDIM, GS, true>(lx, ly, lz, li, act, slot, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB,
+                              SI, SZ, rec, dbar, vq + k0);
+  }
+  // phase 1b: the ring around P (records and div_bar only); slots of points
+  // outside the image or beyond P +- H hold zero cotangents
+  const int hq = gmode ? H : 1;
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    int lx[GR], ly[GR], lz[GR], li[GR];
+    bool act[GR], slot[GR];
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+      const int j = threadIdx.x + (rb * GR + g) * NT;
+      slot[g] = j < NR;
+      ring_point<NDIM>(slot[g] ? j : 0, lx[g], ly[g], lz[g]);
+      li[g] = ((lz[g] + ZH) * QY + (ly[g] + HS)) * QX + (lx[g] + HS);
+      const int qx = x0 + lx[g], qy = y0 + ly[g], qz = z0 + lz[g];
+      act[g] = slot[g] && lx[g] >= -hq && lx[g] < PX + hq && ly[g] >= -hq && ly[g] < PY + hq &&
+               (NDIM == 2 || (lz[g] >= -hq && lz[g] < PZ + hq)) && qx >= 0 && qx < nx && qy >= 0 && qy < ny &&
+               qz >= 0 && qz < nz;
+    }
+    adj_batch<NDIM, GR, false>(lx, ly, lz, li, act, slot, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB,
+                               SI, SZ, rec, dbar, nullptr);
   }
   __syncthreads();
 
@@ -707,12 +828,14 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
 //   Ibar_t = scatter part + sum_c D_c^T (z_t mbar_c)
 // At t = 0 only dH/dp0 = zbar_0 + 2 lambda rho p0 is written. The scatter
 // accumulator is cleared when the next (earlier) step scatters with global
-// atomics.
+// atomics. Voxels are handled in batches whose loads are issued together.
 template <int NDIM>
 __global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                  const float* __restrict__ mbg, const float* __restrict__ stg,
                                                  float* __restrict__ scg, float* __restrict__ abg, EpiArgs A) {
   using B = Blk<NDIM>;
+  constexpr int GS = NDIM == 2 ? EPI_BATCH2 : EPI_BATCH3;
+  static_assert(B::PPT % GS == 0, "batch must divide the voxels per thread");
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -728,50 +851,63 @@ __global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd,
     const float Dn = __uint_as_float(A.dmax[(long long)t.pair * A.T + A.t - 1]);
     clear = A.force_global || !(Dn < (float)B::HS);
   }
+  const int n[3] = {nz, ny, nx};
+  const int s[3] = {sxy, nx, 1};
 #pragma unroll
-  for (int k = 0; k < B::PPT; ++k) {
-    int lx, ly, lz;
-    B::local(threadIdx.x, k, lx, ly, lz);
-    const bool inside = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
-    const int q[3] = {min(t.c + lz, nz - 1), min(t.b + ly, ny - 1), min(t.a + lx, nx - 1)};
-    const int n[3] = {nz, ny, nx};
-    const int s[3] = {sxy, nx, 1};
-    const unsigned idx = (unsigned)((q[0] * ny + q[1]) * nx + q[2]);
-    float zbar = gld(SZ, idx);
-    float Ibar = gld(SI, idx);
+  for (int k0 = 0; k0 < B::PPT; k0 += GS) {
+    int q[GS][3];
+    unsigned idx[GS];
+    bool inside[GS];
+    float si[GS], sz[GS], zc[GS];
+    float m0[GS][NDIM], ip[GS][NDIM], im[GS][NDIM], zu[GS][NDIM], zd[GS][NDIM], mu[GS][NDIM], md[GS][NDIM];
 #pragma unroll
-    for (int c = 0; c < NDIM; ++c) {
-      const int a = 3 - NDIM + c;  // geometric axis of channel c
-      const float* M = MB + c * N;
-      const unsigned sp = (unsigned)up(q[a], n[a], s[a]), sm = (unsigned)dn(q[a], s[a]);
-      const float m0 = gld(M, idx);
-      zbar = fmaf(m0, 0.5f * (gld(I, idx + sp) - gld(I, idx - sm)), zbar);
-      if (!A.first) {
-        // D^T (z m) at q along axis a
-        float dT;
-        const float zc = gld(Z, idx);
-        const float zmu = gld(Z, idx + sp) * gld(M, idx + sp);   // clamped neighbours
-        const float zmd = gld(Z, idx - sm) * gld(M, idx - sm);
-        if (q[a] == 0)
-          dT = -0.5f * (zc * m0 + zmu);
-        else if (q[a] == n[a] - 1)
-          dT = 0.5f * (zmd + zc * m0);
-        else
-          dT = 0.5f * (zmd - zmu);
-        Ibar += dT;
+    for (int g = 0; g < GS; ++g) {
+      int lx, ly, lz;
+      B::local(threadIdx.x, k0 + g, lx, ly, lz);
+      inside[g] = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
+      q[g][0] = min(t.c + lz, nz - 1); q[g][1] = min(t.b + ly, ny - 1); q[g][2] = min(t.a + lx, nx - 1);
+      idx[g] = (unsigned)((q[g][0] * ny + q[g][1]) * nx + q[g][2]);
+      sz[g] = gld(SZ, idx[g]);
+      si[g] = gld(SI, idx[g]);
+      zc[g] = gld(Z, idx[g]);
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) {
+        const int a = 3 - NDIM + c;  // geometric axis of channel c
+        const float* M = MB + c * N;
+        const unsigned sp = (unsigned)up(q[g][a], n[a], s[a]), sm = (unsigned)dn(q[g][a], s[a]);
+        m0[g][c] = gld(M, idx[g]);
+        ip[g][c] = gld(I, idx[g] + sp);
+        im[g][c] = gld(I, idx[g] - sm);
+        zu[g][c] = gld(Z, idx[g] + sp);   // clamped neighbours
+        zd[g][c] = gld(Z, idx[g] - sm);
+        mu[g][c] = gld(M, idx[g] + sp);
+        md[g][c] = gld(M, idx[g] - sm);
       }
     }
-    if (!inside) continue;
-    if (A.first) {
-      if (P.outG) gst(P.outG, idx, fmaf(2.f * P.lam * P.rho, gld(Z, idx), zbar));
-    } else {
-      float* __restrict__ AB = abg + 2 * P.off;
-      gst(AB, idx, Ibar);
-      gst(AB, N + idx, zbar);
-    }
-    if (clear) {
-      gst(SI, idx, 0.f);
-      gst(SZ, idx, 0.f);
+#pragma unroll
+    for (int g = 0; g < GS; ++g) {
+      float zbar = sz[g], Ibar = si[g];
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) {
+        const int a = 3 - NDIM + c;
+        zbar = fmaf(m0[g][c], 0.5f * (ip[g][c] - im[g][c]), zbar);
+        // D^T (z m) at q along axis a
+        const float zmu = zu[g][c] * mu[g][c], zmd = zd[g][c] * md[g][c], zm = zc[g] * m0[g][c];
+        const bool lo = q[g][a] == 0, hi = q[g][a] == n[a] - 1;
+        Ibar += lo ? -0.5f * (zm + zmu) : (hi ? 0.5f * (zmd + zm) : 0.5f * (zmd - zmu));
+      }
+      if (!inside[g]) continue;
+      if (A.first) {
+        if (P.outG) gst(P.outG, idx[g], fmaf(2.f * P.lam * P.rho, zc[g], zbar));
+      } else {
+        float* __restrict__ ABo = abg + 2 * P.off;
+        gst(ABo, idx[g], Ibar);
+        gst(ABo, N + idx[g], zbar);
+      }
+      if (clear) {
+        gst(SI, idx[g], 0.f);
+        gst(SZ, idx[g], 0.f);
+      }
     }
   }
 }

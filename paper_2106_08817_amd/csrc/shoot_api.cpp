@@ -245,11 +245,12 @@ void build_wave(shoot_plan_s* p, Wave& w) {
           for (int x0 = 0; x0 < P.nx; x0 += BX) w.tb.push_back(Tile{pi, x0, y0, z0});
     }
     P.elem_count = (int)w.tb.size() - P.elem_first;
-    // x-pass tiles: rows of the pair; ~512 groups of four outputs per block,
-    // within the LDS budget
+    // x-pass tiles: rows of the pair; as many rows as one batch of the fill
+    // covers (XSEG 64-column segments per wave), within the LDS budget
     const size_t rb = xpass_row_bytes(p->ndim, P.nx, P.ntap4);
-    const int G4 = (P.nx + 3) / 4;
-    int nr = std::max(1, (512 + G4 - 1) / G4);
+    const int L = 4 * ((P.nx + 3) / 4 + P.ntap4);
+    const int nch = (L + 63) / 64;
+    int nr = std::max(1, XSEG * (NT / 64) / nch);
     nr = std::min(nr, std::max(1, (int)(XPASS_LDS_CAP / rb)));
     P.xrows = nr;
     const int rows = P.nz * P.ny;

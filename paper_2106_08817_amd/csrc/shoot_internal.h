@@ -18,11 +18,23 @@ constexpr int NT = 256;
 // thread produces SRB consecutive outputs along it.
 constexpr int SRB = 16;
 constexpr int SSEG = (NT / 64) * SRB;                  // 64 outputs per tile
+// Rows per thread whose loads the strided pass's fill keeps in flight at once
+// (one batch covers tiles up to radius 15).
+constexpr int SFILL = 24;
+// x-pass: 64-column segments per wave whose loads are in flight at once; the
+// host sizes x-pass tiles so one batch fills a tile where the row allows.
+constexpr int XSEG = 6;
 // Block tiles of the elementwise kernels (init, advect, adjoint, epilogue):
 // 1024 voxels, four per thread, x fastest. The adjoint gathers in LDS while
 // the per-step displacement bound is below BLK*_HS pixels.
 constexpr int BLK2_X = 32, BLK2_Y = 32, BLK2_HS = 2;
 constexpr int BLK3_X = 32, BLK3_Y = 8, BLK3_Z = 4, BLK3_HS = 1;
+// Voxels per load batch of the elementwise kernels (a batch's loads are in
+// flight together; larger batches trade registers, hence occupancy, for
+// memory-level parallelism per wave).
+constexpr int ADV_BATCH2 = 2, ADV_BATCH3 = 1;
+constexpr int ADJ_BATCH2 = 2, ADJ_BATCH3 = 1, ADJ_RING_BATCH2 = 2, ADJ_RING_BATCH3 = 1;
+constexpr int EPI_BATCH2 = 4, EPI_BATCH3 = 2;
 // arrival points staged per adjoint tile: the tile grown by the bound on each side
 template <int NDIM>
 constexpr int ADJ_NQ() {
