@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0, help="extra plan flags (bit mask of SHOOT_*)")
     ap.add_argument("--no-extra", action="store_true", help="skip the full-store and single-pair lines")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run a plain copy of MB MiB (counter calibration) and exit")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -264,6 +265,12 @@ def main():
           f"(inputs {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
 
     plan = build_plan(wl, args.flags, torch, api)
+    tuning = None
+    if not args.no_autotune:
+        t_tune = time.perf_counter()
+        tuning = plan.autotune()
+        print(f"[bench] autotune: choices {tuning} ({time.perf_counter() - t_tune:.1f} s)", file=sys.stderr,
+              flush=True)
     for _ in range(args.warmup):
         plan.grad()
     torch.cuda.synchronize()
@@ -306,6 +313,8 @@ def main():
     extra = {}
     if not args.no_extra:
         fplan = build_plan(wl, api.SHOOT_FULL_STORE | args.flags, torch, api)
+        if tuning is not None:
+            fplan.tuning = tuning
         for _ in range(args.warmup):
             fplan.grad()
         fsecs = time_evals(fplan, args.steps, torch)
@@ -316,6 +325,8 @@ def main():
         if args.workload != "c2":
             w2 = synthetic.workload("c2", p0_kind="realistic")
             p2 = build_plan(w2, args.flags, torch, api)
+            if not args.no_autotune:
+                p2.autotune()
             for _ in range(args.warmup):
                 p2.grad()
             n2 = max(args.steps, 20)
@@ -363,7 +374,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "pairs": len(wl.pairs),
                    "voxels": voxels, "T": wl.T, "p0": "realistic (smooth, ~0.3 px per step)",
-                   "flags": args.flags, "mode": "batched tile lists, sqrt(T) checkpoints, captured HIP graph"},
+                   "flags": args.flags, "mode": "batched tile lists, sqrt(T) checkpoints, captured HIP graph",
+                   "tuning": tuning},
         "pair_evals_per_s": len(wl.pairs) * args.steps / secs,
         "step_algorithmic_GBps": step_bytes / (ms_per_step / 1000.0) / 1e9,
         "step_hbm_frac": step_bytes / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBPS,

@@ -138,11 +138,32 @@ shoot_status shoot_plan_waves(shoot_plan plan, int32_t* waves);
 shoot_status shoot_plan_bind(shoot_plan plan, void* workspace, size_t bytes, void* stream);
 
 /*
- * Pick the fastest launch shapes for this plan on the current device by
- * timing the candidate kernels with HIP events on `stream` (synchronising).
- * Results do not depend on the choice (bit-identical outputs). Optional.
+ * Launch-shape tuning. A plan carries SHOOT_TUNE_COUNT choices, each 0 or 1
+ * (0 = default), in this order:
+ *   [0] x-pass rows per tile (one full fill batch / half of it)
+ *   [1] strided (y/z) pass outputs per thread (16 / 8)
+ *   [2] advection load batch, [3] adjoint load batch, [4] adjoint-epilogue
+ *       load batch (voxels per thread whose loads are in flight together)
+ * Every choice computes each output with the same operations in the same
+ * order, so results are bit-identical whatever is chosen.
+ */
+#define SHOOT_TUNE_COUNT 5
+
+/*
+ * Pick the faster option of every tuning choice for this plan on the current
+ * device: runs the plan's evaluation (the gradient when every pair has a
+ * target and out_grad, else the forward shot; outputs are written as by that
+ * call) with each option, timing every kernel with HIP events on `stream`,
+ * and keeps an option other than the default only when it is at least 3 %
+ * faster. Synchronising; not allowed while `stream` is being captured; a
+ * no-op for SHOOT_UNFUSED plans. Optional.
  */
 shoot_status shoot_autotune(shoot_plan plan, void* stream);
+
+/* Read / set the plan's tuning choices (arrays of SHOOT_TUNE_COUNT values;
+ * each must be 0 or 1). Setting discards the plan's captured graphs. */
+shoot_status shoot_plan_get_tuning(shoot_plan plan, int32_t* choices);
+shoot_status shoot_plan_set_tuning(shoot_plan plan, const int32_t* choices);
 
 /*
  * Shoot every pair: writes out_image (I_T) and out_momentum (z_T) when not

@@ -33,6 +33,7 @@ SHOOT_FULL_STORE = 1
 SHOOT_UNFUSED = 2
 SHOOT_NO_GRAPH = 4
 SHOOT_FORCE_GLOBAL_SCATTER = 8
+SHOOT_TUNE_COUNT = 5
 
 # Every function the header declares, with its ctypes signature.
 EXPORTS = {
@@ -43,6 +44,8 @@ EXPORTS = {
     "shoot_plan_waves": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_plan_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "shoot_autotune": (c_int32, [c_void_p, c_void_p]),
+    "shoot_plan_get_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "shoot_plan_set_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_forward": (c_int32, [c_void_p, c_void_p]),
     "shoot_cost": (c_int32, [c_void_p, c_void_p]),
     "shoot_grad_p0": (c_int32, [c_void_p, c_void_p]),

@@ -152,8 +152,26 @@ class Plan:
         """Cost and dH/dp0 of every pair (hand-written discrete adjoint)."""
         self._call(self._lib.shoot_grad_p0, "shoot_grad_p0", stream)
 
-    def autotune(self, stream=None) -> None:
+    def autotune(self, stream=None) -> list:
+        """Time both options of every launch-shape choice and keep the faster
+        ones (bit-identical results); returns the chosen tuning."""
         self._call(self._lib.shoot_autotune, "shoot_autotune", stream)
+        return self.tuning
+
+    @property
+    def tuning(self) -> list:
+        """The plan's launch-shape choices (SHOOT_TUNE_COUNT values, each 0 or 1)."""
+        arr = (ctypes.c_int32 * _lib.SHOOT_TUNE_COUNT)()
+        _lib.check(self._lib.shoot_plan_get_tuning(self._plan, arr), "shoot_plan_get_tuning")
+        return [int(v) for v in arr]
+
+    @tuning.setter
+    def tuning(self, choices) -> None:
+        vals = [int(v) for v in choices]
+        if len(vals) != _lib.SHOOT_TUNE_COUNT:
+            raise ValueError(f"expected {_lib.SHOOT_TUNE_COUNT} tuning choices, got {len(vals)}")
+        arr = (ctypes.c_int32 * _lib.SHOOT_TUNE_COUNT)(*vals)
+        _lib.check(self._lib.shoot_plan_set_tuning(self._plan, arr), "shoot_plan_set_tuning")
 
     def set_profiling(self, enable: bool) -> None:
         """Eager launches with a HIP event pair around each kernel (diagnostics)."""

@@ -50,11 +50,13 @@ hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s);
 hipError_t launch_init(int ndim, const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s);
 hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* tl, int nt, size_t lds,
                         const float* src, float* dst, hipStream_t s);
-hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds,
-                        const float* src, float* dst, const float* extra, hipStream_t s);
-hipError_t launch_advect(int ndim, int nt, const AdvectArgs& a, hipStream_t s);
-hipError_t launch_adv_adj(int ndim, int nt, const AdjArgs& a, hipStream_t s);
-hipError_t launch_epilogue(int ndim, int nt, const EpiArgs& a, hipStream_t s);
+// rb: strided-pass outputs per thread (one of SPASS_RB); opt: tuning option
+// (0 or 1) selecting the load batch of the elementwise kernels.
+hipError_t launch_spass(int ndim, bool passz, int mode, int rb, const PairDev* pd, const Tile* tl, int nt,
+                        size_t lds, const float* src, float* dst, const float* extra, hipStream_t s);
+hipError_t launch_advect(int ndim, int opt, int nt, const AdvectArgs& a, hipStream_t s);
+hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream_t s);
+hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStream_t s);
 hipError_t launch_finalize(int npairs, const PairDev* pd, const float* red_reg, const float* red_ssd,
                            hipStream_t s);
 

@@ -22,6 +22,12 @@
 #include "kernels.h"
 #include "device_common.h"
 
+// No implicit multiply-add contraction in this file: every fused operation is
+// an explicit fmaf, so an output's arithmetic does not depend on how the
+// compiler schedules a particular launch-shape variant (the tuning options are
+// bit-identical).
+#pragma clang fp contract(off)
+
 namespace shoot {
 
 // Geometry of the block tiles shared by the elementwise kernels.
@@ -203,13 +209,13 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
 // Gaussian pass along a strided axis (y, or z in 3-D)
 // ----------------------------------------------------------------------------
 //
-// A tile is 64 consecutive x (one per lane) x SSEG outputs along the pass axis
-// at one index of the third axis, for the channel blockIdx.y. The input is
-// staged in LDS as (SSEG + 4 ntap4) rows x 64 floats; LDS row j holds the
-// input at s = s0 - r + j. Each thread produces SRB consecutive outputs.
+// A tile is 64 consecutive x (one per lane) x SEG = 4 RB outputs along the
+// pass axis at one index of the third axis, for the channel blockIdx.y. The
+// input is staged in LDS as (SEG + 4 ntap4) rows x 64 floats; LDS row j holds
+// the input at s = s0 - r + j. Each thread produces RB consecutive outputs.
 // MODE 0: plain pass. MODE 1: negated (v = -G m). MODE 2: negated, plus
 // -2 lambda * extra (the regulariser's cotangent at t = 0).
-template <int NDIM, bool PASSZ, int MODE>
+template <int NDIM, bool PASSZ, int MODE, int RB>
 __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst,
                                               const float* __restrict__ extra) {
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const int x = t.a + lane;
   const bool xin = x < nx;
   const int s0 = t.c;
-  const int rows = SSEG + 4 * ntap4;
+  const int rows = (NT / 64) * RB + 4 * ntap4;
   const int c = blockIdx.y;  // one channel per block
   const unsigned base = (unsigned)t.b * so + (unsigned)min(x, nx - 1);
   const float* __restrict__ Fc = src + NDIM * P.off + c * N;
@@ -250,18 +256,18 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   }
   __syncthreads();
 
-  float acc[SRB];
+  float acc[RB];
 #pragma unroll
-  for (int i = 0; i < SRB; ++i) acc[i] = 0.f;
+  for (int i = 0; i < RB; ++i) acc[i] = 0.f;
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
-  const float* col = lds + (wv * SRB) * 64 + lane;
+  const float* col = lds + (wv * RB) * 64 + lane;
   for (int b = 0; b < ntap4; ++b) {
     const float4 w = W4[b];
-    float win[SRB + 3];
+    float win[RB + 3];
 #pragma unroll
-    for (int j = 0; j < SRB + 3; ++j) win[j] = col[(4 * b + j) * 64];
+    for (int j = 0; j < RB + 3; ++j) win[j] = col[(4 * b + j) * 64];
 #pragma unroll
-    for (int i = 0; i < SRB; ++i) {
+    for (int i = 0; i < RB; ++i) {
       acc[i] = fmaf(w.x, win[i], acc[i]);
       acc[i] = fmaf(w.y, win[i + 1], acc[i]);
       acc[i] = fmaf(w.z, win[i + 2], acc[i]);
@@ -273,8 +279,8 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
     const float* __restrict__ Ec = (MODE == 2 && extra != nullptr) ? extra + NDIM * P.off + c * N : nullptr;
     const float escale = -2.f * P.lam;
 #pragma unroll
-    for (int i = 0; i < SRB; ++i) {
-      const int s = s0 + wv * SRB + i;
+    for (int i = 0; i < RB; ++i) {
+      const int s = s0 + wv * RB + i;
       if (s < ns) {
         const unsigned idx = base + (unsigned)s * ss;
         float o = acc[i];
@@ -317,8 +323,8 @@ __device__ __forceinline__ void load_v_div(const float* __restrict__ V, unsigned
 template <int NDIM>
 __device__ __forceinline__ float div_of(const float vn[2 * NDIM]) {
   float d = 0.5f * (vn[0] - vn[1]);
-  d += 0.5f * (vn[2] - vn[3]);
-  if (NDIM == 3) d += 0.5f * (vn[4] - vn[5]);
+  d = fmaf(0.5f, vn[2] - vn[3], d);
+  if (NDIM == 3) d = fmaf(0.5f, vn[4] - vn[5], d);
   return d;
 }
 
@@ -327,18 +333,17 @@ __device__ __forceinline__ float div_of(const float vn[2 * NDIM]) {
 template <int NDIM>
 __device__ __forceinline__ float mlerp(const float* c, const float f[3]) {
   const float wx0 = 1.f - f[2], wx1 = f[2], wy0 = 1.f - f[1], wy1 = f[1];
-  const float a = wy0 * (wx0 * c[0] + wx1 * c[1]) + wy1 * (wx0 * c[2] + wx1 * c[3]);
+  const float a = fmaf(wy1, fmaf(wx1, c[3], wx0 * c[2]), wy0 * fmaf(wx1, c[1], wx0 * c[0]));
   if (NDIM == 2) return a;
-  const float b = wy0 * (wx0 * c[4] + wx1 * c[5]) + wy1 * (wx0 * c[6] + wx1 * c[7]);
-  return (1.f - f[0]) * a + f[0] * b;
+  const float b = fmaf(wy1, fmaf(wx1, c[7], wx0 * c[6]), wy0 * fmaf(wx1, c[5], wx0 * c[4]));
+  return fmaf(f[0], b, (1.f - f[0]) * a);
 }
 
-template <int NDIM>
+template <int NDIM, int GS>
 __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                const float* __restrict__ Vg, const float* __restrict__ stg,
                                                float* __restrict__ stog, AdvectArgs A) {
   using B = Blk<NDIM>;
-  constexpr int GS = NDIM == 2 ? ADV_BATCH2 : ADV_BATCH3;
   constexpr int NC = NDIM == 3 ? 8 : 4;
   static_assert(B::PPT % GS == 0, "batch must divide the voxels per thread");
   __shared__ float sh[NT / 64];
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
       const float Ih = mlerp<NDIM>(iv[g], fr[g]);
       const float zh = mlerp<NDIM>(zv[g], fr[g]);
       In[g] = fmaf(rdt, zh, Ih);
-      zn[g] = zh * (1.f - dt * div_of<NDIM>(vn[g]));
+      zn[g] = zh * fmaf(-dt, div_of<NDIM>(vn[g]), 1.f);
     }
 #pragma unroll
     for (int g = 0; g < GS; ++g) {
@@ -427,7 +432,7 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
         float mv = 0.f;
 #pragma unroll
         for (int c = 0; c < NDIM; ++c) mv = fmaf(zq0 * gr[c], v[g][c], mv);
-        reg += P.rho * zq0 * zq0 - mv;
+        reg += fmaf(P.rho * zq0, zq0, -mv);
       }
     }
     if (A.last) {
@@ -622,7 +627,7 @@ __device__ __forceinline__ void adj_batch(const int (&lx)[G], const int (&ly)[G]
   for (int g = 0; g < G; ++g) {
     const float fr[3] = {az[g].f, ay[g].f, ax[g].f};
     const float zh = mlerp<NDIM>(zv[g], fr);
-    const float zhb = fmaf(rdt, ib[g], (1.f - dt * div_of<NDIM>(vn[g])) * zb[g]);
+    const float zhb = fmaf(rdt, ib[g], fmaf(-dt, div_of<NDIM>(vn[g]), 1.f) * zb[g]);
     const bool inP1 = lx[g] >= -1 && lx[g] <= B::X && ly[g] >= -1 && ly[g] <= B::Y &&
                       (NDIM == 2 || (lz[g] >= -1 && lz[g] <= B::Z));
     if (act[g] && inP1) dbar[((lz[g] + ZO) * DY + (ly[g] + 1)) * DX + (lx[g] + 1)] = -dt * zh * zb[g];
@@ -692,7 +697,7 @@ __device__ __forceinline__ void cand3(const Rec<NDIM>& rec, int rp, float& accI,
   cand_acc<NDIM>(rec, r, a, tap3<OX>(a[0]), tap3<OY>(a[1]), NDIM == 3 ? tap3<OZ>(a[2]) : 1.f, accI, accZ);
 }
 
-template <int NDIM>
+template <int NDIM, int GS>
 __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__ pd, const Tile* __restrict__ tla,
                                                      const float* __restrict__ Vg, const float* __restrict__ stg,
                                                      const float* __restrict__ abg, float* __restrict__ scg,
@@ -706,7 +711,6 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   constexpr int NR = NQ - B::NP;  // ring slots
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int ZH = NDIM == 3 ? HS : 0;
-  constexpr int GS = NDIM == 2 ? ADJ_BATCH2 : ADJ_BATCH3;  // own points per batch
   constexpr int GR = NDIM == 2 ? ADJ_RING_BATCH2 : ADJ_RING_BATCH3;  // ring points per batch
   constexpr int NRB = (NR + GR * NT - 1) / (GR * NT);   // ring batches
   static_assert(PPT % GS == 0, "batch must divide the voxels per thread");
@@ -829,12 +833,11 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
 // At t = 0 only dH/dp0 = zbar_0 + 2 lambda rho p0 is written. The scatter
 // accumulator is cleared when the next (earlier) step scatters with global
 // atomics. Voxels are handled in batches whose loads are issued together.
-template <int NDIM>
+template <int NDIM, int GS>
 __global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                  const float* __restrict__ mbg, const float* __restrict__ stg,
                                                  float* __restrict__ scg, float* __restrict__ abg, EpiArgs A) {
   using B = Blk<NDIM>;
-  constexpr int GS = NDIM == 2 ? EPI_BATCH2 : EPI_BATCH3;
   static_assert(B::PPT % GS == 0, "batch must divide the voxels per thread");
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
@@ -964,38 +967,61 @@ hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* t
   return post();
 }
 
+template <int NDIM, bool PASSZ, int MODE>
+static void spass_rb(int rb, dim3 grid, size_t lds, const PairDev* pd, const Tile* tl, const float* src, float* dst,
+                     const float* extra, hipStream_t s) {
+  if (rb == 8) k_spass<NDIM, PASSZ, MODE, 8><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
+  else k_spass<NDIM, PASSZ, MODE, 16><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
+}
+
 template <int NDIM, bool PASSZ>
-static void spass_dispatch(int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds, const float* src,
+static void spass_dispatch(int mode, int rb, const PairDev* pd, const Tile* tl, int nt, size_t lds, const float* src,
                            float* dst, const float* extra, hipStream_t s) {
   const dim3 grid(nt, NDIM);
-  if (mode == 0) k_spass<NDIM, PASSZ, 0><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
-  else if (mode == 1) k_spass<NDIM, PASSZ, 1><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
-  else k_spass<NDIM, PASSZ, 2><<<grid, NT, lds, s>>>(pd, tl, src, dst, extra);
+  if (mode == 0) spass_rb<NDIM, PASSZ, 0>(rb, grid, lds, pd, tl, src, dst, extra, s);
+  else if (mode == 1) spass_rb<NDIM, PASSZ, 1>(rb, grid, lds, pd, tl, src, dst, extra, s);
+  else spass_rb<NDIM, PASSZ, 2>(rb, grid, lds, pd, tl, src, dst, extra, s);
 }
 
-hipError_t launch_spass(int ndim, bool passz, int mode, const PairDev* pd, const Tile* tl, int nt, size_t lds,
-                        const float* src, float* dst, const float* extra, hipStream_t s) {
-  if (ndim == 2) spass_dispatch<2, false>(mode, pd, tl, nt, lds, src, dst, extra, s);
-  else if (passz) spass_dispatch<3, true>(mode, pd, tl, nt, lds, src, dst, extra, s);
-  else spass_dispatch<3, false>(mode, pd, tl, nt, lds, src, dst, extra, s);
+hipError_t launch_spass(int ndim, bool passz, int mode, int rb, const PairDev* pd, const Tile* tl, int nt,
+                        size_t lds, const float* src, float* dst, const float* extra, hipStream_t s) {
+  if (rb != 8 && rb != 16) return hipErrorInvalidValue;
+  if (ndim == 2) spass_dispatch<2, false>(mode, rb, pd, tl, nt, lds, src, dst, extra, s);
+  else if (passz) spass_dispatch<3, true>(mode, rb, pd, tl, nt, lds, src, dst, extra, s);
+  else spass_dispatch<3, false>(mode, rb, pd, tl, nt, lds, src, dst, extra, s);
   return post();
 }
 
-hipError_t launch_advect(int ndim, int nt, const AdvectArgs& a, hipStream_t s) {
-  if (ndim == 2) k_advect<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
-  else k_advect<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+hipError_t launch_advect(int ndim, int opt, int nt, const AdvectArgs& a, hipStream_t s) {
+  if (ndim == 2) {
+    if (opt == 0) k_advect<2, ADV_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    else k_advect<2, ADV_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+  } else {
+    if (opt == 0) k_advect<3, ADV_BATCH[1][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    else k_advect<3, ADV_BATCH[1][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+  }
   return post();
 }
 
-hipError_t launch_adv_adj(int ndim, int nt, const AdjArgs& a, hipStream_t s) {
-  if (ndim == 2) k_adv_adj_tile<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
-  else k_adv_adj_tile<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream_t s) {
+  if (ndim == 2) {
+    if (opt == 0) k_adv_adj_tile<2, ADJ_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+    else k_adv_adj_tile<2, ADJ_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+  } else {
+    if (opt == 0) k_adv_adj_tile<3, ADJ_BATCH[1][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+    else k_adv_adj_tile<3, ADJ_BATCH[1][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+  }
   return post();
 }
 
-hipError_t launch_epilogue(int ndim, int nt, const EpiArgs& a, hipStream_t s) {
-  if (ndim == 2) k_epilogue<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
-  else k_epilogue<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStream_t s) {
+  if (ndim == 2) {
+    if (opt == 0) k_epilogue<2, EPI_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+    else k_epilogue<2, EPI_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+  } else {
+    if (opt == 0) k_epilogue<3, EPI_BATCH[1][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+    else k_epilogue<3, EPI_BATCH[1][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+  }
   return post();
 }
 

@@ -46,11 +46,13 @@ enum Op { OP_FORWARD = 0, OP_COST = 1, OP_GRAD = 2 };
 struct Wave {
   std::vector<int> ids;
   std::vector<PairDev> pdev;
-  std::vector<Tile> tb, tx, ty, tz;
-  long long ntot = 0;                // padded voxel total
-  size_t lds_x = 0, lds_y = 0, lds_z = 0;
+  std::vector<Tile> tb;
+  std::vector<Tile> tx[2], ty[2], tz[2];  // per tuning option of the x-pass / strided passes
+  long long ntot = 0;                     // padded voxel total
+  size_t lds_x[2] = {0, 0}, lds_y[2] = {0, 0}, lds_z[2] = {0, 0};
   // header offsets (bytes from the workspace base)
-  size_t o_pd = 0, o_tb = 0, o_tx = 0, o_ty = 0, o_tz = 0, o_dmax = 0, o_rreg = 0, o_rssd = 0;
+  size_t o_pd = 0, o_tb = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
+  size_t o_dmax = 0, o_rreg = 0, o_rssd = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
 };
@@ -138,6 +140,7 @@ struct shoot_plan_s {
   unfused::Plan* uf = nullptr;      // SHOOT_UNFUSED state
   bool profiling = false;
   Prof prof;
+  int tune[TUNE_N] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -213,9 +216,12 @@ shoot_status validate(const shoot_pair* pairs, int32_t n, int32_t T) {
 
 // Builds descriptors and tile lists of one wave (header offsets are set later).
 void build_wave(shoot_plan_s* p, Wave& w) {
-  w.pdev.clear(); w.tb.clear(); w.tx.clear(); w.ty.clear(); w.tz.clear();
+  w.pdev.clear(); w.tb.clear();
+  for (int o = 0; o < 2; ++o) {
+    w.tx[o].clear(); w.ty[o].clear(); w.tz[o].clear();
+    w.lds_x[o] = w.lds_y[o] = w.lds_z[o] = 0;
+  }
   long long off = 0;
-  w.lds_x = w.lds_y = w.lds_z = 0;
   for (size_t li = 0; li < w.ids.size(); ++li) {
     const shoot_pair& q = p->pairs[w.ids[li]];
     PairDev P;
@@ -245,31 +251,38 @@ void build_wave(shoot_plan_s* p, Wave& w) {
           for (int x0 = 0; x0 < P.nx; x0 += BX) w.tb.push_back(Tile{pi, x0, y0, z0});
     }
     P.elem_count = (int)w.tb.size() - P.elem_first;
-    // x-pass tiles: rows of the pair; as many rows as one batch of the fill
-    // covers (XSEG 64-column segments per wave), within the LDS budget
+    // x-pass tiles: rows of the pair. Option 0: as many rows as one batch of
+    // the fill covers (XSEG 64-column segments per wave); option 1: half of
+    // that. Both within the LDS budget.
     const size_t rb = xpass_row_bytes(p->ndim, P.nx, P.ntap4);
     const int L = 4 * ((P.nx + 3) / 4 + P.ntap4);
     const int nch = (L + 63) / 64;
-    int nr = std::max(1, XSEG * (NT / 64) / nch);
-    nr = std::min(nr, std::max(1, (int)(XPASS_LDS_CAP / rb)));
-    P.xrows = nr;
     const int rows = P.nz * P.ny;
-    for (int r0 = 0; r0 < rows; r0 += nr) {
-      const int cnt = std::min(nr, rows - r0);
-      w.tx.push_back(Tile{pi, r0, cnt, 0});
-      w.lds_x = std::max(w.lds_x, rb * (size_t)cnt);
+    for (int opt = 0; opt < 2; ++opt) {
+      int nr = std::max(1, XSEG * (NT / 64) / nch);
+      if (opt == 1) nr = std::max(1, nr / 2);
+      nr = std::min(nr, std::max(1, (int)(XPASS_LDS_CAP / rb)));
+      if (opt == 0) P.xrows = nr;
+      for (int r0 = 0; r0 < rows; r0 += nr) {
+        const int cnt = std::min(nr, rows - r0);
+        w.tx[opt].push_back(Tile{pi, r0, cnt, 0});
+        w.lds_x[opt] = std::max(w.lds_x[opt], rb * (size_t)cnt);
+      }
     }
-    // strided passes
-    const size_t sb = (size_t)(SSEG + 4 * P.ntap4) * 64 * sizeof(float);
-    for (int o = 0; o < P.nz; ++o)
-      for (int x0 = 0; x0 < P.nx; x0 += 64)
-        for (int s0 = 0; s0 < P.ny; s0 += SSEG) w.ty.push_back(Tile{pi, x0, o, s0});
-    w.lds_y = std::max(w.lds_y, sb);
-    if (p->ndim == 3) {
-      for (int o = 0; o < P.ny; ++o)
+    // strided passes: tiles of 4 RB outputs along the pass axis
+    for (int opt = 0; opt < 2; ++opt) {
+      const int seg = (NT / 64) * SPASS_RB[opt];
+      const size_t sb = (size_t)(seg + 4 * P.ntap4) * 64 * sizeof(float);
+      for (int o = 0; o < P.nz; ++o)
         for (int x0 = 0; x0 < P.nx; x0 += 64)
-          for (int s0 = 0; s0 < P.nz; s0 += SSEG) w.tz.push_back(Tile{pi, x0, o, s0});
-      w.lds_z = std::max(w.lds_z, sb);
+          for (int s0 = 0; s0 < P.ny; s0 += seg) w.ty[opt].push_back(Tile{pi, x0, o, s0});
+      w.lds_y[opt] = std::max(w.lds_y[opt], sb);
+      if (p->ndim == 3) {
+        for (int o = 0; o < P.ny; ++o)
+          for (int x0 = 0; x0 < P.nx; x0 += 64)
+            for (int s0 = 0; s0 < P.nz; s0 += seg) w.tz[opt].push_back(Tile{pi, x0, o, s0});
+        w.lds_z[opt] = std::max(w.lds_z[opt], sb);
+      }
     }
     w.pdev.push_back(P);
   }
@@ -282,9 +295,11 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, ALIGN); return r; };
   w.o_pd = take(w.pdev.size() * sizeof(PairDev));
   w.o_tb = take(w.tb.size() * sizeof(Tile));
-  w.o_tx = take(w.tx.size() * sizeof(Tile));
-  w.o_ty = take(w.ty.size() * sizeof(Tile));
-  w.o_tz = take(w.tz.size() * sizeof(Tile));
+  for (int o = 0; o < 2; ++o) {
+    w.o_tx[o] = take(w.tx[o].size() * sizeof(Tile));
+    w.o_ty[o] = take(w.ty[o].size() * sizeof(Tile));
+    w.o_tz[o] = take(w.tz[o].size() * sizeof(Tile));
+  }
   w.o_dmax = take(w.pdev.size() * (size_t)p->T * sizeof(unsigned));
   w.o_rreg = take(w.tb.size() * sizeof(float));
   w.o_rssd = take(w.tb.size() * sizeof(float));
@@ -301,6 +316,9 @@ struct Ctx {
   const PairDev* pd;
   const Tile *tb, *tx, *ty, *tz;
   int ntb, ntx, nty, ntz;
+  size_t lds_x, lds_y, lds_z;
+  int rb;                 // strided-pass outputs per thread
+  int o_adv, o_adj, o_epi;  // load-batch options
   unsigned* dmax;
   float *rreg, *rssd;
   float *st, *vs, *u, *u2, *ab, *sc, *vb;
@@ -314,9 +332,12 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   char* b = p->ws;
   c.pd = (const PairDev*)(b + w.o_pd);
   c.tb = (const Tile*)(b + w.o_tb); c.ntb = (int)w.tb.size();
-  c.tx = (const Tile*)(b + w.o_tx); c.ntx = (int)w.tx.size();
-  c.ty = (const Tile*)(b + w.o_ty); c.nty = (int)w.ty.size();
-  c.tz = (const Tile*)(b + w.o_tz); c.ntz = (int)w.tz.size();
+  const int ox = p->tune[TUNE_XPASS], os = p->tune[TUNE_SPASS];
+  c.tx = (const Tile*)(b + w.o_tx[ox]); c.ntx = (int)w.tx[ox].size(); c.lds_x = w.lds_x[ox];
+  c.ty = (const Tile*)(b + w.o_ty[os]); c.nty = (int)w.ty[os].size(); c.lds_y = w.lds_y[os];
+  c.tz = (const Tile*)(b + w.o_tz[os]); c.ntz = (int)w.tz[os].size(); c.lds_z = w.lds_z[os];
+  c.rb = SPASS_RB[os];
+  c.o_adv = p->tune[TUNE_ADVECT]; c.o_adj = p->tune[TUNE_ADJ]; c.o_epi = p->tune[TUNE_EPI];
   c.dmax = (unsigned*)(b + w.o_dmax);
   c.rreg = (float*)(b + w.o_rreg);
   c.rssd = (float*)(b + w.o_rssd);
@@ -347,13 +368,13 @@ float* AB(const Ctx& c, int t) { return c.ab + (size_t)(t & 1) * 2 * c.ntot; }
 // v_t = -G (z_t grad I_t) into the v slot of t.
 hipError_t velocity(const Ctx& c, int t) {
   const int nd = c.p->ndim;
-  LAUNCH(KI_XPASS_M, launch_xpass(nd, true, c.pd, c.tx, c.ntx, c.w->lds_x, ST(c, t), c.u, c.s));
+  LAUNCH(KI_XPASS_M, launch_xpass(nd, true, c.pd, c.tx, c.ntx, c.lds_x, ST(c, t), c.u, c.s));
   if (nd == 2) {
-    LAUNCH(KI_SPASS_V, launch_spass(2, false, 1, c.pd, c.ty, c.nty, c.w->lds_y, c.u, VS(c, t), nullptr, c.s));
+    LAUNCH(KI_SPASS_V, launch_spass(2, false, 1, c.rb, c.pd, c.ty, c.nty, c.lds_y, c.u, VS(c, t), nullptr, c.s));
     return hipSuccess;
   }
-  LAUNCH(KI_SPASS_MID, launch_spass(3, false, 0, c.pd, c.ty, c.nty, c.w->lds_y, c.u, c.u2, nullptr, c.s));
-  LAUNCH(KI_SPASS_V, launch_spass(3, true, 1, c.pd, c.tz, c.ntz, c.w->lds_z, c.u2, VS(c, t), nullptr, c.s));
+  LAUNCH(KI_SPASS_MID, launch_spass(3, false, 0, c.rb, c.pd, c.ty, c.nty, c.lds_y, c.u, c.u2, nullptr, c.s));
+  LAUNCH(KI_SPASS_V, launch_spass(3, true, 1, c.rb, c.pd, c.tz, c.ntz, c.lds_z, c.u2, VS(c, t), nullptr, c.s));
   return hipSuccess;
 }
 
@@ -371,7 +392,7 @@ hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
   a.red_reg = (first_pass && t == 0) ? c.rreg : nullptr;
   a.red_ssd = (first_pass && t == T - 1) ? c.rssd : nullptr;
   if (a.last && op == OP_GRAD) { a.ab_out = AB(c, T); a.sc_zero = c.sc; }
-  LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.ntb, a, c.s));
+  LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.o_adv, c.ntb, a, c.s));
   return hipSuccess;
 }
 
@@ -395,22 +416,22 @@ hipError_t bwd_step(const Ctx& c, int t) {
   a.pd = c.pd; a.tl = c.tb; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
   a.sc = c.sc; a.vb = c.vb;
   a.dmax = c.dmax; a.T = c.p->T; a.t = t; a.force_global = force;
-  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.ntb, a, c.s));
+  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.o_adj, c.ntb, a, c.s));
   // mbar = -G vbar (+ -2 lambda v_0 at t = 0), written back into vb
-  LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.w->lds_x, c.vb, c.u, c.s));
+  LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.lds_x, c.vb, c.u, c.s));
   const float* extra = t == 0 ? VS(c, 0) : nullptr;
   if (nd == 2) {
-    LAUNCH(KI_SPASS_MBAR, launch_spass(2, false, 2, c.pd, c.ty, c.nty, c.w->lds_y, c.u, c.vb, extra, c.s));
+    LAUNCH(KI_SPASS_MBAR, launch_spass(2, false, 2, c.rb, c.pd, c.ty, c.nty, c.lds_y, c.u, c.vb, extra, c.s));
   } else {
-    LAUNCH(KI_SPASS_MID, launch_spass(3, false, 0, c.pd, c.ty, c.nty, c.w->lds_y, c.u, c.u2, nullptr, c.s));
-    LAUNCH(KI_SPASS_MBAR, launch_spass(3, true, 2, c.pd, c.tz, c.ntz, c.w->lds_z, c.u2, c.vb, extra, c.s));
+    LAUNCH(KI_SPASS_MID, launch_spass(3, false, 0, c.rb, c.pd, c.ty, c.nty, c.lds_y, c.u, c.u2, nullptr, c.s));
+    LAUNCH(KI_SPASS_MBAR, launch_spass(3, true, 2, c.rb, c.pd, c.tz, c.ntz, c.lds_z, c.u2, c.vb, extra, c.s));
   }
   EpiArgs ep{};
   ep.pd = c.pd; ep.tl = c.tb; ep.mb = c.vb; ep.st = ST(c, t); ep.sc = c.sc;
   ep.ab_out = t > 0 ? AB(c, t) : nullptr;
   ep.dmax = c.dmax; ep.T = c.p->T; ep.t = t; ep.force_global = force;
   ep.first = t == 0 ? 1 : 0;
-  LAUNCH(KI_EPILOGUE, launch_epilogue(nd, c.ntb, ep, c.s));
+  LAUNCH(KI_EPILOGUE, launch_epilogue(nd, c.o_epi, c.ntb, ep, c.s));
   return hipSuccess;
 }
 
@@ -591,9 +612,11 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     };
     put(w.o_pd, w.pdev.data(), w.pdev.size() * sizeof(PairDev));
     put(w.o_tb, w.tb.data(), w.tb.size() * sizeof(Tile));
-    put(w.o_tx, w.tx.data(), w.tx.size() * sizeof(Tile));
-    put(w.o_ty, w.ty.data(), w.ty.size() * sizeof(Tile));
-    put(w.o_tz, w.tz.data(), w.tz.size() * sizeof(Tile));
+    for (int o = 0; o < 2; ++o) {
+      put(w.o_tx[o], w.tx[o].data(), w.tx[o].size() * sizeof(Tile));
+      put(w.o_ty[o], w.ty[o].data(), w.ty[o].size() * sizeof(Tile));
+      put(w.o_tz[o], w.tz[o].data(), w.tz[o].size() * sizeof(Tile));
+    }
   }
   *out = p;
   g_err.clear();
@@ -639,9 +662,72 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
 }
 
 shoot_status shoot_autotune(shoot_plan p, void* stream) {
+  static_assert(SHOOT_TUNE_COUNT == TUNE_N, "tuning choices of the header and the runtime differ");
   if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
   if (!p->ws) return fail(SHOOT_E_STATE, "plan is not bound to a workspace");
-  (void)stream;
+  if (p->uf) return SHOOT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s) HIPCHK(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(SHOOT_E_STATE, "autotune cannot run under stream capture");
+  int op = OP_GRAD;
+  for (const shoot_pair& q : p->pairs)
+    if (!q.target || !q.out_grad) op = OP_FORWARD;
+  // kernel families timed for each choice
+  static const int fam[TUNE_N][3] = {
+      {KI_XPASS_M, KI_XPASS_V, -1},
+      {KI_SPASS_MID, KI_SPASS_V, KI_SPASS_MBAR},
+      {KI_ADVECT, -1, -1},
+      {KI_ADV_ADJ, -1, -1},
+      {KI_EPILOGUE, -1, -1}};
+  const bool was_profiling = p->profiling;
+  long long saved_n[KI_COUNT];
+  double saved_ms[KI_COUNT];
+  for (int i = 0; i < KI_COUNT; ++i) { saved_n[i] = p->prof.launches[i]; saved_ms[i] = p->prof.ms[i]; }
+  int saved_tune[TUNE_N];
+  for (int k = 0; k < TUNE_N; ++k) saved_tune[k] = p->tune[k];
+  auto restore = [&](bool keep_tune) {
+    p->profiling = was_profiling;
+    for (int i = 0; i < KI_COUNT; ++i) { p->prof.launches[i] = saved_n[i]; p->prof.ms[i] = saved_ms[i]; }
+    if (!keep_tune)
+      for (int k = 0; k < TUNE_N; ++k) p->tune[k] = saved_tune[k];
+    drop_graphs(p);
+  };
+  double t[TUNE_N][2] = {};
+  p->profiling = true;
+  for (int opt = 0; opt < 2; ++opt) {
+    for (int k = 0; k < TUNE_N; ++k) p->tune[k] = opt;
+    for (int rep = 0; rep < 4; ++rep) {  // the first evaluation warms up and is not counted
+      for (int i = 0; i < KI_COUNT; ++i) { p->prof.launches[i] = 0; p->prof.ms[i] = 0.0; }
+      shoot_status st = execute(p, op, stream);
+      if (st != SHOOT_OK) {
+        restore(false);
+        return st;
+      }
+      if (rep == 0) continue;
+      for (int k = 0; k < TUNE_N; ++k)
+        for (int j = 0; j < 3; ++j)
+          if (fam[k][j] >= 0) t[k][opt] += p->prof.ms[fam[k][j]];
+    }
+  }
+  for (int k = 0; k < TUNE_N; ++k) p->tune[k] = (t[k][0] > 0.0 && t[k][1] < 0.97 * t[k][0]) ? 1 : 0;
+  restore(true);
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_get_tuning(shoot_plan p, int32_t* choices) {
+  if (!p || !choices) return fail(SHOOT_E_ARG, "NULL argument");
+  for (int k = 0; k < TUNE_N; ++k) choices[k] = p->tune[k];
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_set_tuning(shoot_plan p, const int32_t* choices) {
+  if (!p || !choices) return fail(SHOOT_E_ARG, "NULL argument");
+  for (int k = 0; k < TUNE_N; ++k)
+    if (choices[k] != 0 && choices[k] != 1)
+      return fail(SHOOT_E_ARG, "tuning choice " + std::to_string(k) + " must be 0 or 1");
+  for (int k = 0; k < TUNE_N; ++k) p->tune[k] = choices[k];
+  drop_graphs(p);
   return SHOOT_OK;
 }
 

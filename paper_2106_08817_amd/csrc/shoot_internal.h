@@ -15,9 +15,8 @@ constexpr int WPAD = 4 * ((2 * RMAX + 1 + 3) / 4);   // 64
 // Threads per block for every kernel.
 constexpr int NT = 256;
 // Strided-pass tile: 64 lanes along x, NT/64 waves along the pass axis, each
-// thread produces SRB consecutive outputs along it.
-constexpr int SRB = 16;
-constexpr int SSEG = (NT / 64) * SRB;                  // 64 outputs per tile
+// thread produces RB consecutive outputs along it (RB is a tuning option).
+constexpr int SPASS_RB[2] = {16, 8};
 // Rows per thread whose loads the strided pass's fill keeps in flight at once
 // (one batch covers tiles up to radius 15).
 constexpr int SFILL = 24;
@@ -31,10 +30,15 @@ constexpr int BLK2_X = 32, BLK2_Y = 32, BLK2_HS = 2;
 constexpr int BLK3_X = 32, BLK3_Y = 8, BLK3_Z = 4, BLK3_HS = 1;
 // Voxels per load batch of the elementwise kernels (a batch's loads are in
 // flight together; larger batches trade registers, hence occupancy, for
-// memory-level parallelism per wave).
-constexpr int ADV_BATCH2 = 2, ADV_BATCH3 = 1;
-constexpr int ADJ_BATCH2 = 2, ADJ_BATCH3 = 1, ADJ_RING_BATCH2 = 2, ADJ_RING_BATCH3 = 1;
-constexpr int EPI_BATCH2 = 4, EPI_BATCH3 = 2;
+// memory-level parallelism per wave), per tuning option: [ndim - 2][option].
+constexpr int ADV_BATCH[2][2] = {{2, 4}, {1, 2}};
+constexpr int ADJ_BATCH[2][2] = {{2, 4}, {1, 2}};
+constexpr int ADJ_RING_BATCH2 = 2, ADJ_RING_BATCH3 = 1;
+constexpr int EPI_BATCH[2][2] = {{4, 2}, {2, 1}};
+// Tuning choices of a plan (each 0 or 1; 0 is the default): x-pass rows per
+// tile (full fill batch / half), strided-pass outputs per thread
+// (SPASS_RB), and the load batches of advect, adjoint and epilogue.
+enum TuneKnob { TUNE_XPASS = 0, TUNE_SPASS, TUNE_ADVECT, TUNE_ADJ, TUNE_EPI, TUNE_N };
 // arrival points staged per adjoint tile: the tile grown by the bound on each side
 template <int NDIM>
 constexpr int ADJ_NQ() {

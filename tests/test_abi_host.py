@@ -126,3 +126,22 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load()
+
+
+def test_tuning_choices_host_side():
+    lib = _lib.load()
+    st, h = create([pair(shape=(96, 128))], T=6)
+    assert st == _lib.SHOOT_OK
+    arr = (ctypes.c_int32 * _lib.SHOOT_TUNE_COUNT)()
+    assert lib.shoot_plan_get_tuning(h, arr) == _lib.SHOOT_OK
+    assert list(arr) == [0] * _lib.SHOOT_TUNE_COUNT            # defaults
+    want = [1, 0, 1, 1, 0]
+    assert lib.shoot_plan_set_tuning(h, (ctypes.c_int32 * 5)(*want)) == _lib.SHOOT_OK
+    assert lib.shoot_plan_get_tuning(h, arr) == _lib.SHOOT_OK and list(arr) == want
+    assert lib.shoot_plan_set_tuning(h, (ctypes.c_int32 * 5)(0, 2, 0, 0, 0)) == _lib.SHOOT_E_ARG
+    assert lib.shoot_plan_get_tuning(h, arr) == _lib.SHOOT_OK and list(arr) == want   # unchanged
+    assert lib.shoot_plan_set_tuning(h, None) == _lib.SHOOT_E_ARG
+    assert lib.shoot_plan_get_tuning(None, arr) == _lib.SHOOT_E_ARG
+    # autotune needs a bound workspace
+    assert lib.shoot_autotune(h, None) == _lib.SHOOT_E_STATE
+    lib.shoot_plan_destroy(h)
