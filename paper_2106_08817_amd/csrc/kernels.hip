@@ -494,10 +494,15 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
 // For D >= HS (or when forced) the block instead scatters its own q with
 // global atomics into the accumulator, which the previous adjoint step (or
 // the last forward step) cleared.
+// (D^T g) at index j of an axis of length n (stride s in the LDS array):
+// 0.5 (g[j-1] - g[j+1]) inside, -0.5 (g[0] + g[1]) at j = 0 and
+// 0.5 (g[n-2] + g[n-1]) at j = n - 1, written with selects (both neighbours
+// are always inside the staged P +- 1 array).
 __device__ __forceinline__ float diffT_lds(const float* g, int b, int j, int n, int s) {
-  if (j == 0) return -0.5f * (g[b] + g[b + s]);
-  if (j == n - 1) return 0.5f * (g[b - s] + g[b]);
-  return 0.5f * (g[b - s] - g[b + s]);
+  const float c = g[b];
+  const float lo = j == 0 ? -c : g[b - s];
+  const float hi = j == n - 1 ? -c : g[b + s];
+  return 0.5f * (lo - hi);
 }
 
 // Record of one arrival point q for the gather: the foot's offset from q per
@@ -751,6 +756,13 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
     adj_batch<NDIM, GS, true>(lx, ly, lz, li, act, slot, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB,
                               SI, SZ, rec, dbar, vq + k0);
   }
+  // Materialise the foot-point parts of vbar here: otherwise the compiler
+  // sinks their arithmetic past the barrier and keeps every corner value live
+  // across it (far more registers than the NDIM results).
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+#pragma unroll
+    for (int c = 0; c < NDIM; ++c) asm volatile("" : "+v"(vq[k][c]));
   // phase 1b: the ring around P (records and div_bar only); slots of points
   // outside the image or beyond P +- H hold zero cotangents
   const int hq = gmode ? H : 1;
@@ -774,55 +786,65 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   }
   __syncthreads();
 
-  // phase 2: vbar and the gathered transpose of the interpolation
+  // phase 2: vbar and the gathered transpose of the interpolation, for every
+  // output of the thread (outputs beyond the image are computed on clamped
+  // indices and not stored)
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     int lx, ly, lz;
     B::local(threadIdx.x, k, lx, ly, lz);
     const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
-    if (qx >= nx || qy >= ny || qz >= nz) continue;
-    const unsigned idx = (unsigned)((qz * ny + qy) * nx + qx);
+    const bool inside = qx < nx && qy < ny && qz < nz;
+    const unsigned idx = (unsigned)((min(qz, nz - 1) * ny + min(qy, ny - 1)) * nx + min(qx, nx - 1));
     const int b = ((lz + ZO) * DY + (ly + 1)) * DX + (lx + 1);
-    gst(VB, (NDIM - 1) * N + idx, vq[k][NDIM - 1] + diffT_lds(dbar, b, qx, nx, 1));
-    gst(VB, (NDIM - 2) * N + idx, vq[k][NDIM - 2] + diffT_lds(dbar, b, qy, ny, DX));
-    if (NDIM == 3) gst(VB, idx, vq[k][0] + diffT_lds(dbar, b, qz, nz, DX * DY));
-    if (!gmode) continue;
+    float vb[NDIM];
+    vb[NDIM - 1] = vq[k][NDIM - 1] + diffT_lds(dbar, b, qx, nx, 1);
+    vb[NDIM - 2] = vq[k][NDIM - 2] + diffT_lds(dbar, b, qy, ny, DX);
+    if (NDIM == 3) vb[0] = vq[k][0] + diffT_lds(dbar, b, qz, nz, DX * DY);
     // Interp^T at p: sum over the arrival points q = p - o, |o| <= H per axis
-    const int rp = ((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS);
     float accI = 0.f, accZ = 0.f;
-    if (H == 1) {
-      // fixed 3^d stencil, fixed order
-      if (NDIM == 3) {
-        cand3<NDIM, -1, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, -1, -1, 0>(rec, rp, accI, accZ);
-        cand3<NDIM, -1, -1, 1>(rec, rp, accI, accZ); cand3<NDIM, -1, 0, -1>(rec, rp, accI, accZ);
-        cand3<NDIM, -1, 0, 0>(rec, rp, accI, accZ);  cand3<NDIM, -1, 0, 1>(rec, rp, accI, accZ);
-        cand3<NDIM, -1, 1, -1>(rec, rp, accI, accZ); cand3<NDIM, -1, 1, 0>(rec, rp, accI, accZ);
-        cand3<NDIM, -1, 1, 1>(rec, rp, accI, accZ);
-        cand3<NDIM, 1, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, 1, -1, 0>(rec, rp, accI, accZ);
-        cand3<NDIM, 1, -1, 1>(rec, rp, accI, accZ);  cand3<NDIM, 1, 0, -1>(rec, rp, accI, accZ);
-        cand3<NDIM, 1, 0, 0>(rec, rp, accI, accZ);   cand3<NDIM, 1, 0, 1>(rec, rp, accI, accZ);
-        cand3<NDIM, 1, 1, -1>(rec, rp, accI, accZ);  cand3<NDIM, 1, 1, 0>(rec, rp, accI, accZ);
-        cand3<NDIM, 1, 1, 1>(rec, rp, accI, accZ);
+    if (gmode) {
+      const int rp = ((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS);
+      if (H == 1) {
+        // fixed 3^d stencil, fixed order
+        if (NDIM == 3) {
+          cand3<NDIM, -1, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, -1, -1, 0>(rec, rp, accI, accZ);
+          cand3<NDIM, -1, -1, 1>(rec, rp, accI, accZ); cand3<NDIM, -1, 0, -1>(rec, rp, accI, accZ);
+          cand3<NDIM, -1, 0, 0>(rec, rp, accI, accZ);  cand3<NDIM, -1, 0, 1>(rec, rp, accI, accZ);
+          cand3<NDIM, -1, 1, -1>(rec, rp, accI, accZ); cand3<NDIM, -1, 1, 0>(rec, rp, accI, accZ);
+          cand3<NDIM, -1, 1, 1>(rec, rp, accI, accZ);
+          cand3<NDIM, 1, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, 1, -1, 0>(rec, rp, accI, accZ);
+          cand3<NDIM, 1, -1, 1>(rec, rp, accI, accZ);  cand3<NDIM, 1, 0, -1>(rec, rp, accI, accZ);
+          cand3<NDIM, 1, 0, 0>(rec, rp, accI, accZ);   cand3<NDIM, 1, 0, 1>(rec, rp, accI, accZ);
+          cand3<NDIM, 1, 1, -1>(rec, rp, accI, accZ);  cand3<NDIM, 1, 1, 0>(rec, rp, accI, accZ);
+          cand3<NDIM, 1, 1, 1>(rec, rp, accI, accZ);
+        }
+        cand3<NDIM, 0, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, 0, -1, 0>(rec, rp, accI, accZ);
+        cand3<NDIM, 0, -1, 1>(rec, rp, accI, accZ);  cand3<NDIM, 0, 0, -1>(rec, rp, accI, accZ);
+        cand3<NDIM, 0, 0, 0>(rec, rp, accI, accZ);   cand3<NDIM, 0, 0, 1>(rec, rp, accI, accZ);
+        cand3<NDIM, 0, 1, -1>(rec, rp, accI, accZ);  cand3<NDIM, 0, 1, 0>(rec, rp, accI, accZ);
+        cand3<NDIM, 0, 1, 1>(rec, rp, accI, accZ);
+      } else {
+        // general bound (2-D, 1 <= D < HS): hat weights over (2H + 1)^d offsets
+        const int hz = NDIM == 3 ? H : 0;
+        for (int oz = -hz; oz <= hz; ++oz)
+          for (int oy = -H; oy <= H; ++oy)
+            for (int ox = -H; ox <= H; ++ox) {
+              const int r = rp - (oz * QY + oy) * QX - ox;
+              const vf4 a = rec.v[r];
+              cand_acc<NDIM>(rec, r, a, hat(a[0] - (float)ox), hat(a[1] - (float)oy),
+                             NDIM == 3 ? hat(a[2] - (float)oz) : 1.f, accI, accZ);
+            }
       }
-      cand3<NDIM, 0, -1, -1>(rec, rp, accI, accZ); cand3<NDIM, 0, -1, 0>(rec, rp, accI, accZ);
-      cand3<NDIM, 0, -1, 1>(rec, rp, accI, accZ);  cand3<NDIM, 0, 0, -1>(rec, rp, accI, accZ);
-      cand3<NDIM, 0, 0, 0>(rec, rp, accI, accZ);   cand3<NDIM, 0, 0, 1>(rec, rp, accI, accZ);
-      cand3<NDIM, 0, 1, -1>(rec, rp, accI, accZ);  cand3<NDIM, 0, 1, 0>(rec, rp, accI, accZ);
-      cand3<NDIM, 0, 1, 1>(rec, rp, accI, accZ);
-    } else {
-      // general bound (2-D, 1 <= D < HS): hat weights over (2H + 1)^d offsets
-      const int hz = NDIM == 3 ? H : 0;
-      for (int oz = -hz; oz <= hz; ++oz)
-        for (int oy = -H; oy <= H; ++oy)
-          for (int ox = -H; ox <= H; ++ox) {
-            const int r = rp - (oz * QY + oy) * QX - ox;
-            const vf4 a = rec.v[r];
-            cand_acc<NDIM>(rec, r, a, hat(a[0] - (float)ox), hat(a[1] - (float)oy),
-                           NDIM == 3 ? hat(a[2] - (float)oz) : 1.f, accI, accZ);
-          }
     }
-    gst(SI, idx, accI);
-    gst(SZ, idx, accZ);
+    if (inside) {
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) gst(VB, c * N + idx, vb[c]);
+      if (gmode) {
+        gst(SI, idx, accI);
+        gst(SZ, idx, accZ);
+      }
+    }
   }
 }
 
