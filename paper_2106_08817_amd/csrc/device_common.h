@@ -65,9 +65,10 @@ __device__ __forceinline__ int up(int j, int n, int s) { return j + 1 < n ? s : 
 __device__ __forceinline__ int dn(int j, int s) { return j > 0 ? s : 0; }
 
 // One axis of a foot point in local form: the foot is q + d with d = -dt v.
-// The integer part comes from floor(d) alone, so no absolute coordinate is
-// ever rounded. Clamping follows c = clamp(q + d, 0, n - 1),
-// i = min(floor(c), n - 2), f = c - i; live = 1 iff 0 < q + d < n - 1.
+// The clamped offset e = clamp(d, -q, n - 1 - q) = clamp(q + d, 0, n - 1) - q
+// is formed without rounding any absolute coordinate; the cell is
+// i = min(q + floor(e), n - 2) and the fraction f = q + e - i (1 when the
+// foot sits on the last grid line). live = 1 iff 0 < q + d < n - 1 (strict).
 struct Axis {
   int i;       // cell index
   float f;     // fraction in [0, 1]
@@ -75,16 +76,15 @@ struct Axis {
 };
 
 __device__ __forceinline__ Axis foot_axis(int q, float d, int n) {
-  d = fminf(fmaxf(d, -1.0e7f), 1.0e7f);
-  const float kf = floorf(d);
-  const float fl = d - kf;            // in [0, 1]; may round to 1 for tiny negative d
+  const float lo = (float)(-q), hi = (float)(n - 1 - q);
+  const float e = fminf(fmaxf(d, lo), hi);  // NaN d gives lo
+  const float kf = floorf(e);
   const int yb = q + (int)kf;
-  const bool lo = yb < 0, hi = yb >= n - 1;
-  const bool edge = (yb == 0 && fl == 0.f) || (yb == n - 2 && fl >= 1.f);
+  const bool top = yb > n - 2;              // only when the foot is on the last line
   Axis a;
-  a.i = lo ? 0 : (hi ? n - 2 : yb);
-  a.f = lo ? 0.f : (hi ? 1.f : fl);
-  a.live = (lo || hi || edge) ? 0.f : 1.f;
+  a.i = top ? n - 2 : yb;
+  a.f = top ? 1.f : e - kf;
+  a.live = (d > lo && d < hi) ? 1.f : 0.f;
   return a;
 }
 

@@ -535,45 +535,51 @@ __device__ __forceinline__ float tap3(float e) {
 
 __device__ __forceinline__ float hat(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
 
-// Slot of the j-th point of the ring P +- HS minus P (ring order: the HS
-// full planes / rows on each side, then the sides of the remaining ones), as
-// local coordinates relative to the tile origin.
-template <int NDIM>
+// The j-th point of the ring P +- W minus P (ring order: the W full planes /
+// rows on each side, then the sides of the remaining ones), as local
+// coordinates relative to the tile origin; RING_N<NDIM, W>() points in all.
+template <int NDIM, int W>
+__host__ __device__ constexpr int RING_N() {
+  using B = Blk<NDIM>;
+  return (B::X + 2 * W) * (B::Y + 2 * W) * (NDIM == 3 ? B::Z + 2 * W : 1) - B::NP;
+}
+
+template <int NDIM, int W>
 __host__ __device__ __forceinline__ void ring_point(int j, int& lx, int& ly, int& lz) {
   using B = Blk<NDIM>;
-  constexpr int HS = B::HS, QX = B::X + 2 * HS, QY = B::Y + 2 * HS, QZ = B::Z + 2 * HS;
+  constexpr int QX = B::X + 2 * W, QY = B::Y + 2 * W, QZ = B::Z + 2 * W;
   constexpr int R2 = QX * QY - B::X * B::Y;  // ring of one plane
   int qzl = 0;
   if (NDIM == 3) {
     constexpr int FP = QX * QY;
-    if (j < 2 * HS * FP) {
+    if (j < 2 * W * FP) {
       const int pl = j / FP;
-      qzl = pl < HS ? pl : QZ - 2 * HS + pl;
+      qzl = pl < W ? pl : QZ - 2 * W + pl;
       j -= pl * FP;
-      ly = j / QX - HS;
-      lx = j % QX - HS;
-      lz = qzl - HS;
+      ly = j / QX - W;
+      lx = j % QX - W;
+      lz = qzl - W;
       return;
     }
-    j -= 2 * HS * FP;
-    qzl = HS + j / R2;
+    j -= 2 * W * FP;
+    qzl = W + j / R2;
     j %= R2;
   }
-  constexpr int TOP = HS * QX;
+  constexpr int TOP = W * QX;
   int qyl, qxl;
   if (j < 2 * TOP) {
     const int rw = j / QX;
-    qyl = rw < HS ? rw : QY - 2 * HS + rw;
+    qyl = rw < W ? rw : QY - 2 * W + rw;
     qxl = j % QX;
   } else {
     j -= 2 * TOP;
-    qyl = HS + j / (2 * HS);
-    const int c = j % (2 * HS);
-    qxl = c < HS ? c : B::X + c;
+    qyl = W + j / (2 * W);
+    const int c = j % (2 * W);
+    qxl = c < W ? c : B::X + c;
   }
-  lx = qxl - HS;
-  ly = qyl - HS;
-  lz = NDIM == 3 ? qzl - HS : 0;
+  lx = qxl - W;
+  ly = qyl - W;
+  lz = NDIM == 3 ? qzl - W : 0;
 }
 
 // Phase-1 work of the adjoint for a batch of G arrival points (local
@@ -702,6 +708,38 @@ __device__ __forceinline__ void cand3(const Rec<NDIM>& rec, int rp, float& accI,
   cand_acc<NDIM>(rec, r, a, tap3<OX>(a[0]), tap3<OY>(a[1]), NDIM == 3 ? tap3<OZ>(a[2]) : 1.f, accI, accZ);
 }
 
+// Phase 1 over the ring P +- W minus P in batches of G points per thread.
+template <int NDIM, int W, int G>
+__device__ __forceinline__ void adj_ring(int hq, bool gmode, int x0, int y0, int z0, int nx, int ny, int nz,
+                                         unsigned N, float dt, float rdt, const float* __restrict__ V,
+                                         const float* __restrict__ I, const float* __restrict__ Z,
+                                         const float* __restrict__ AB, float* __restrict__ SI,
+                                         float* __restrict__ SZ, const Rec<NDIM>& rec, float* dbar) {
+  using B = Blk<NDIM>;
+  constexpr int HS = B::HS, QX = B::X + 2 * HS, QY = B::Y + 2 * HS;
+  constexpr int ZH = NDIM == 3 ? HS : 0;
+  constexpr int NR = RING_N<NDIM, W>();
+  constexpr int NRB = (NR + G * NT - 1) / (G * NT);
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    int lx[G], ly[G], lz[G], li[G];
+    bool act[G], slot[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = threadIdx.x + (rb * G + g) * NT;
+      slot[g] = j < NR;
+      ring_point<NDIM, W>(slot[g] ? j : 0, lx[g], ly[g], lz[g]);
+      li[g] = ((lz[g] + ZH) * QY + (ly[g] + HS)) * QX + (lx[g] + HS);
+      const int qx = x0 + lx[g], qy = y0 + ly[g], qz = z0 + lz[g];
+      act[g] = slot[g] && lx[g] >= -hq && lx[g] < B::X + hq && ly[g] >= -hq && ly[g] < B::Y + hq &&
+               (NDIM == 2 || (lz[g] >= -hq && lz[g] < B::Z + hq)) && qx >= 0 && qx < nx && qy >= 0 &&
+               qy < ny && qz >= 0 && qz < nz;
+    }
+    adj_batch<NDIM, G, false>(lx, ly, lz, li, act, slot, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB,
+                              SI, SZ, rec, dbar, nullptr);
+  }
+}
+
 template <int NDIM, int GS>
 __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__ pd, const Tile* __restrict__ tla,
                                                      const float* __restrict__ Vg, const float* __restrict__ stg,
@@ -713,11 +751,9 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   constexpr int DX = PX + 2, DY = PY + 2, DZ = NDIM == 3 ? PZ + 2 : 1;
   constexpr int QX = PX + 2 * HS, QY = PY + 2 * HS;
   constexpr int NQ = ADJ_NQ<NDIM>();
-  constexpr int NR = NQ - B::NP;  // ring slots
   constexpr int ZO = NDIM == 3 ? 1 : 0;
   constexpr int ZH = NDIM == 3 ? HS : 0;
   constexpr int GR = NDIM == 2 ? ADJ_RING_BATCH2 : ADJ_RING_BATCH3;  // ring points per batch
-  constexpr int NRB = (NR + GR * NT - 1) / (GR * NT);   // ring batches
   static_assert(PPT % GS == 0, "batch must divide the voxels per thread");
   __shared__ vf4 rvec[NQ];
   __shared__ float rzb[NDIM == 3 ? NQ : 1];
@@ -766,23 +802,20 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   // phase 1b: the ring around P (records and div_bar only); slots of points
   // outside the image or beyond P +- H hold zero cotangents
   const int hq = gmode ? H : 1;
-#pragma unroll
-  for (int rb = 0; rb < NRB; ++rb) {
-    int lx[GR], ly[GR], lz[GR], li[GR];
-    bool act[GR], slot[GR];
-#pragma unroll
-    for (int g = 0; g < GR; ++g) {
-      const int j = threadIdx.x + (rb * GR + g) * NT;
-      slot[g] = j < NR;
-      ring_point<NDIM>(slot[g] ? j : 0, lx[g], ly[g], lz[g]);
-      li[g] = ((lz[g] + ZH) * QY + (ly[g] + HS)) * QX + (lx[g] + HS);
-      const int qx = x0 + lx[g], qy = y0 + ly[g], qz = z0 + lz[g];
-      act[g] = slot[g] && lx[g] >= -hq && lx[g] < PX + hq && ly[g] >= -hq && ly[g] < PY + hq &&
-               (NDIM == 2 || (lz[g] >= -hq && lz[g] < PZ + hq)) && qx >= 0 && qx < nx && qy >= 0 && qy < ny &&
-               qz >= 0 && qz < nz;
+  if (hq == HS) {
+    adj_ring<NDIM, HS, GR>(hq, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ, rec, dbar);
+  } else {
+    // H = 1 below a wider staged bound (2-D): visit the width-1 ring, then
+    // clear the record slots of the outer ring
+    adj_ring<NDIM, 1, 1>(hq, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB, SI, SZ, rec, dbar);
+    if (gmode) {
+      for (int j = threadIdx.x; j < RING_N<NDIM, HS>(); j += NT) {
+        int lx, ly, lz;
+        ring_point<NDIM, HS>(j, lx, ly, lz);
+        const bool outer = lx < -1 || lx > PX || ly < -1 || ly > PY || (NDIM == 3 && (lz < -1 || lz > PZ));
+        if (outer) rec.clear(((lz + ZH) * QY + (ly + HS)) * QX + (lx + HS));
+      }
     }
-    adj_batch<NDIM, GR, false>(lx, ly, lz, li, act, slot, gmode, x0, y0, z0, nx, ny, nz, N, dt, rdt, V, I, Z, AB,
-                               SI, SZ, rec, dbar, nullptr);
   }
   __syncthreads();
 
