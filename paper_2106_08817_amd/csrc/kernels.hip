@@ -473,6 +473,214 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
   }
 }
 
+// Staged-tile advection. The block stages I and z on P +- 1 and each velocity
+// channel with a halo of one cell along its own axis (clamped into the image,
+// which is exactly the clamping of the central difference), all with
+// coalesced loads. When the block's largest displacement is below one cell,
+// every foot's corners lie in P +- 1 and are read from LDS; otherwise they are
+// gathered from global memory. Same arithmetic as k_advect.
+template <int NDIM>
+__global__ __launch_bounds__(NT) void k_advect_lds(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
+                                                   const float* __restrict__ Vg, const float* __restrict__ stg,
+                                                   float* __restrict__ stog, AdvectArgs A) {
+  using B = Blk<NDIM>;
+  constexpr int X = B::X, Y = B::Y, Z = B::Z, PPT = B::PPT;
+  constexpr int NC = NDIM == 3 ? 8 : 4;
+  constexpr int SX = X + 2, SY = Y + 2, SZ = NDIM == 3 ? Z + 2 : 1;  // P +- 1
+  constexpr int NS = SX * SY * SZ;
+  constexpr int NVX = SX * Y * Z, NVY = X * SY * Z, NVZ = NDIM == 3 ? X * Y * (Z + 2) : 1;
+  constexpr int UI = (NS + NT - 1) / NT, UX = (NVX + NT - 1) / NT, UY = (NVY + NT - 1) / NT;
+  constexpr int UZ = NDIM == 3 ? (NVZ + NT - 1) / NT : 0;
+  __shared__ float sI[NS], sZ[NS], sVx[NVX], sVy[NVY], sVz[NVZ];
+  __shared__ float sh[NT / 64];
+  __shared__ float sD;
+  const int tix = xcd_tile(gridDim.x);
+  const Tile t = tl[tix];
+  const PairDev& P = pd[t.pair];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned N = (unsigned)P.N;
+  const unsigned sxy = (unsigned)(nx * ny);
+  const float dt = P.dt, rdt = P.rho * P.dt;
+  const float* __restrict__ V = Vg + NDIM * P.off;
+  const float* __restrict__ Vx = V + (NDIM - 1) * N;
+  const float* __restrict__ Vy = V + (NDIM - 2) * N;
+  const float* __restrict__ I = stg + 2 * P.off;
+  const float* __restrict__ Zs = I + N;
+  float* __restrict__ Io = stog ? stog + 2 * P.off : nullptr;
+  const int x0 = t.a, y0 = t.b, z0 = t.c;
+  // global index of the box point (bx, by, bz) relative to (x0 + ox, ...), clamped
+  auto gidx = [&](int bx, int by, int bz, int ox, int oy, int oz) -> unsigned {
+    const int gx = clampi(x0 + ox + bx, 0, nx - 1), gy = clampi(y0 + oy + by, 0, ny - 1);
+    const int gz = NDIM == 3 ? clampi(z0 + oz + bz, 0, nz - 1) : 0;
+    return (unsigned)((gz * ny + gy) * nx + gx);
+  };
+  {
+    float a[UI], b[UI], cx[UX], cy[UY], cz[UZ > 0 ? UZ : 1];
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      const int j = min((int)threadIdx.x + u * NT, NS - 1);
+      const unsigned g = gidx(j % SX, (j / SX) % SY, j / (SX * SY), -1, -1, -1);
+      a[u] = gld(I, g);
+      b[u] = gld(Zs, g);
+    }
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      const int j = min((int)threadIdx.x + u * NT, NVX - 1);
+      cx[u] = gld(Vx, gidx(j % SX, (j / SX) % Y, j / (SX * Y), -1, 0, 0));
+    }
+#pragma unroll
+    for (int u = 0; u < UY; ++u) {
+      const int j = min((int)threadIdx.x + u * NT, NVY - 1);
+      cy[u] = gld(Vy, gidx(j % X, (j / X) % SY, j / (X * SY), 0, -1, 0));
+    }
+#pragma unroll
+    for (int u = 0; u < UZ; ++u) {
+      const int j = min((int)threadIdx.x + u * NT, NVZ - 1);
+      cz[u] = gld(V, gidx(j % X, (j / X) % Y, j / (X * Y), 0, 0, -1));
+    }
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      const int j = threadIdx.x + u * NT;
+      if (j < NS) { sI[j] = a[u]; sZ[j] = b[u]; }
+    }
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      const int j = threadIdx.x + u * NT;
+      if (j < NVX) sVx[j] = cx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UY; ++u) {
+      const int j = threadIdx.x + u * NT;
+      if (j < NVY) sVy[j] = cy[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UZ; ++u) {
+      const int j = threadIdx.x + u * NT;
+      if (j < NVZ) sVz[j] = cz[u];
+    }
+  }
+  __syncthreads();
+
+  // velocity, divergence and displacement at the thread's voxels
+  int lq[PPT][3];
+  bool inside[PPT];
+  float v[PPT][NDIM], div[PPT];
+  float dm = 0.f;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    inside[k] = x0 + lx < nx && y0 + ly < ny && z0 + lz < nz;
+    lx = min(lx, nx - 1 - x0); ly = min(ly, ny - 1 - y0); lz = min(lz, nz - 1 - z0);  // clamped into the image
+    lq[k][0] = lz; lq[k][1] = ly; lq[k][2] = lx;
+    const int ix = (lz * Y + ly) * SX + lx + 1, iy = (lz * SY + ly + 1) * X + lx;
+    float vn[2 * NDIM];
+    vn[0] = sVx[ix + 1]; vn[1] = sVx[ix - 1];
+    vn[2] = sVy[iy + X]; vn[3] = sVy[iy - X];
+    v[k][NDIM - 1] = sVx[ix];
+    v[k][NDIM - 2] = sVy[iy];
+    if (NDIM == 3) {
+      const int iz = ((lz + 1) * Y + ly) * X + lx;
+      vn[4] = sVz[iz + X * Y]; vn[5] = sVz[iz - X * Y];
+      v[k][0] = sVz[iz];
+    }
+    div[k] = div_of<NDIM>(vn);
+    float d = 0.f;
+#pragma unroll
+    for (int c = 0; c < NDIM; ++c) d = fmaxf(d, fabsf(-dt * v[k][c]));
+    if (inside[k]) dm = fmaxf(dm, d);
+  }
+  {
+    const float m = block_max(dm, sh);
+    if (threadIdx.x == 0) sD = m;
+    __syncthreads();
+  }
+  const bool staged = sD < 1.f;
+  float reg = 0.f, ssd = 0.f;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int lz = lq[k][0], ly = lq[k][1], lx = lq[k][2];
+    const int qx = x0 + lx, qy = y0 + ly, qz = z0 + lz;
+    const unsigned idx = (unsigned)((qz * ny + qy) * nx + qx);
+    const Axis ax = foot_axis(qx, -dt * v[k][NDIM - 1], nx);
+    const Axis ay = foot_axis(qy, -dt * v[k][NDIM - 2], ny);
+    Axis az;
+    if (NDIM == 3) {
+      az = foot_axis(qz, -dt * v[k][0], nz);
+    } else {
+      az.i = 0; az.f = 0.f; az.live = 0.f;
+    }
+    float iv[NC], zv[NC];
+    if (staged) {
+      const int s0 = ((NDIM == 3 ? az.i - z0 + 1 : 0) * SY + (ay.i - y0 + 1)) * SX + (ax.i - x0 + 1);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int sj = s0 + (j >> 2) * SX * SY + ((j >> 1) & 1) * SX + (j & 1);
+        iv[j] = sI[sj];
+        zv[j] = sZ[sj];
+      }
+    } else {
+      const unsigned c0 = (unsigned)(az.i * (int)sxy + ay.i * nx + ax.i);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const unsigned gi = c0 + (unsigned)(j >> 2) * sxy + (unsigned)(((j >> 1) & 1) * nx + (j & 1));
+        iv[j] = gld(I, gi);
+        zv[j] = gld(Zs, gi);
+      }
+    }
+    const float fr[3] = {az.f, ay.f, ax.f};
+    const float Ih = mlerp<NDIM>(iv, fr);
+    const float zh = mlerp<NDIM>(zv, fr);
+    const float In = fmaf(rdt, zh, Ih);
+    const float zn = zh * fmaf(-dt, div[k], 1.f);
+    if (!inside[k]) continue;
+    if (Io) {
+      gst(Io, idx, In);
+      gst(Io, N + idx, zn);
+    }
+    if (A.red_reg) {
+      // -<m_0, v_0> + rho |p0|^2 at q, with m_c = z D_c I (neighbours from the staged, clamped box)
+      const int sq = ((NDIM == 3 ? lz + 1 : 0) * SY + ly + 1) * SX + lx + 1;
+      const float zq0 = sZ[sq];
+      float gr[NDIM];
+      gr[NDIM - 1] = 0.5f * (sI[sq + 1] - sI[sq - 1]);
+      gr[NDIM - 2] = 0.5f * (sI[sq + SX] - sI[sq - SX]);
+      if (NDIM == 3) gr[0] = 0.5f * (sI[sq + SX * SY] - sI[sq - SX * SY]);
+      float mv = 0.f;
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) mv = fmaf(zq0 * gr[c], v[k][c], mv);
+      reg += fmaf(P.rho * zq0, zq0, -mv);
+    }
+    if (A.last) {
+      if (P.outI) P.outI[idx] = In;
+      if (P.outZ) P.outZ[idx] = zn;
+      if (P.J) {
+        const float R = In - P.J[idx];
+        ssd = fmaf(0.5f * R, R, ssd);
+        if (A.ab_out) {
+          float* AB = A.ab_out + 2 * P.off;
+          AB[idx] = R;
+          AB[N + idx] = 0.f;
+        }
+      }
+      if (A.sc_zero) {
+        float* SC = A.sc_zero + 2 * P.off;
+        SC[idx] = 0.f;
+        SC[N + idx] = 0.f;
+      }
+    }
+  }
+  if (A.red_reg) {
+    const float s2 = block_sum(reg, sh);
+    if (threadIdx.x == 0) A.red_reg[tix] = s2;
+  }
+  if (A.red_ssd) {
+    const float s2 = block_sum(ssd, sh);
+    if (threadIdx.x == 0) A.red_ssd[tix] = s2;
+  }
+  if (A.dmax && threadIdx.x == 0) atomicMax(A.dmax + (long long)t.pair * A.T + A.t, __float_as_uint(sD));
+}
+
 // ----------------------------------------------------------------------------
 // adjoint of the advection, tile-owned, gather form
 // ----------------------------------------------------------------------------
@@ -1049,11 +1257,11 @@ hipError_t launch_spass(int ndim, bool passz, int mode, int rb, const PairDev* p
 
 hipError_t launch_advect(int ndim, int opt, int nt, const AdvectArgs& a, hipStream_t s) {
   if (ndim == 2) {
-    if (opt == 0) k_advect<2, ADV_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
-    else k_advect<2, ADV_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    if (opt == 0) k_advect_lds<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    else k_advect<2, ADV_BATCH[0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
   } else {
-    if (opt == 0) k_advect<3, ADV_BATCH[1][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
-    else k_advect<3, ADV_BATCH[1][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    if (opt == 0) k_advect_lds<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    else k_advect<3, ADV_BATCH[1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
   }
   return post();
 }
