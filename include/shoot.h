@@ -142,8 +142,10 @@ shoot_status shoot_plan_bind(shoot_plan plan, void* workspace, size_t bytes, voi
  * (0 = default), in this order:
  *   [0] x-pass rows per tile (one full fill batch / half of it)
  *   [1] strided (y/z) pass outputs per thread (16 / 8)
- *   [2] advection load batch, [3] adjoint load batch, [4] adjoint-epilogue
- *       load batch (voxels per thread whose loads are in flight together)
+ *   [2] advection: from an LDS-staged tile / by global gathers
+ *   [3] adjoint load batch (voxels per thread whose loads are in flight
+ *       together: 2 / 4 in 2-D, 1 / 2 in 3-D)
+ *   [4] adjoint epilogue: from an LDS-staged tile / by direct loads
  * Every choice computes each output with the same operations in the same
  * order, so results are bit-identical whatever is chosen.
  */

@@ -473,6 +473,85 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
   }
 }
 
+// LDS staging of a block tile: two scalar fields on the box P +- 1 and the
+// NDIM channels of a vector field, the channel of axis a with a halo of one
+// cell along a only. Positions outside the image hold the clamped neighbour,
+// which is exactly the clamping of the central difference. All loads of a
+// thread are issued before the LDS stores.
+template <int NDIM>
+struct Stage {
+  using B = Blk<NDIM>;
+  static constexpr int X = B::X, Y = B::Y, Z = B::Z;
+  static constexpr int SX = X + 2, SY = Y + 2, SZ = NDIM == 3 ? Z + 2 : 1;
+  static constexpr int NS = SX * SY * SZ;
+  static constexpr int NVX = SX * Y * Z, NVY = X * SY * Z, NVZ = NDIM == 3 ? X * Y * (Z + 2) : 1;
+  // box index of local (lx, ly, lz) in P
+  __device__ static int box(int lx, int ly, int lz) { return ((NDIM == 3 ? lz + 1 : 0) * SY + ly + 1) * SX + lx + 1; }
+  __device__ static int vx(int lx, int ly, int lz) { return (lz * Y + ly) * SX + lx + 1; }   // +-1 along x
+  __device__ static int vy(int lx, int ly, int lz) { return (lz * SY + ly + 1) * X + lx; }   // +-X along y
+  __device__ static int vz(int lx, int ly, int lz) { return ((lz + 1) * Y + ly) * X + lx; }  // +-X*Y along z
+};
+
+template <int NDIM>
+__device__ __forceinline__ void stage_tile(int x0, int y0, int z0, int nx, int ny, int nz,
+                                           const float* __restrict__ F0, const float* __restrict__ F1,
+                                           const float* __restrict__ Cx, const float* __restrict__ Cy,
+                                           const float* __restrict__ Cz, float* s0, float* s1, float* sx, float* sy,
+                                           float* sz) {
+  using S = Stage<NDIM>;
+  constexpr int X = S::X, Y = S::Y, SX = S::SX, SY = S::SY;
+  constexpr int UI = (S::NS + NT - 1) / NT, UX = (S::NVX + NT - 1) / NT, UY = (S::NVY + NT - 1) / NT;
+  constexpr int UZ = NDIM == 3 ? (S::NVZ + NT - 1) / NT : 0;
+  auto gidx = [&](int bx, int by, int bz, int ox, int oy, int oz) -> unsigned {
+    const int gx = clampi(x0 + ox + bx, 0, nx - 1), gy = clampi(y0 + oy + by, 0, ny - 1);
+    const int gz = NDIM == 3 ? clampi(z0 + oz + bz, 0, nz - 1) : 0;
+    return (unsigned)((gz * ny + gy) * nx + gx);
+  };
+  float a[UI], b[UI], cx[UX], cy[UY], cz[UZ > 0 ? UZ : 1];
+#pragma unroll
+  for (int u = 0; u < UI; ++u) {
+    const int j = min((int)threadIdx.x + u * NT, S::NS - 1);
+    const unsigned g = gidx(j % SX, (j / SX) % SY, j / (SX * SY), -1, -1, -1);
+    a[u] = gld(F0, g);
+    b[u] = gld(F1, g);
+  }
+#pragma unroll
+  for (int u = 0; u < UX; ++u) {
+    const int j = min((int)threadIdx.x + u * NT, S::NVX - 1);
+    cx[u] = gld(Cx, gidx(j % SX, (j / SX) % Y, j / (SX * Y), -1, 0, 0));
+  }
+#pragma unroll
+  for (int u = 0; u < UY; ++u) {
+    const int j = min((int)threadIdx.x + u * NT, S::NVY - 1);
+    cy[u] = gld(Cy, gidx(j % X, (j / X) % SY, j / (X * SY), 0, -1, 0));
+  }
+#pragma unroll
+  for (int u = 0; u < UZ; ++u) {
+    const int j = min((int)threadIdx.x + u * NT, S::NVZ - 1);
+    cz[u] = gld(Cz, gidx(j % X, (j / X) % Y, j / (X * Y), 0, 0, -1));
+  }
+#pragma unroll
+  for (int u = 0; u < UI; ++u) {
+    const int j = threadIdx.x + u * NT;
+    if (j < S::NS) { s0[j] = a[u]; s1[j] = b[u]; }
+  }
+#pragma unroll
+  for (int u = 0; u < UX; ++u) {
+    const int j = threadIdx.x + u * NT;
+    if (j < S::NVX) sx[j] = cx[u];
+  }
+#pragma unroll
+  for (int u = 0; u < UY; ++u) {
+    const int j = threadIdx.x + u * NT;
+    if (j < S::NVY) sy[j] = cy[u];
+  }
+#pragma unroll
+  for (int u = 0; u < UZ; ++u) {
+    const int j = threadIdx.x + u * NT;
+    if (j < S::NVZ) sz[j] = cz[u];
+  }
+}
+
 // Staged-tile advection. The block stages I and z on P +- 1 and each velocity
 // channel with a halo of one cell along its own axis (clamped into the image,
 // which is exactly the clamping of the central difference), all with
@@ -484,14 +563,11 @@ __global__ __launch_bounds__(NT) void k_advect_lds(const PairDev* __restrict__ p
                                                    const float* __restrict__ Vg, const float* __restrict__ stg,
                                                    float* __restrict__ stog, AdvectArgs A) {
   using B = Blk<NDIM>;
-  constexpr int X = B::X, Y = B::Y, Z = B::Z, PPT = B::PPT;
+  using S = Stage<NDIM>;
+  constexpr int X = B::X, Y = B::Y, PPT = B::PPT;
   constexpr int NC = NDIM == 3 ? 8 : 4;
-  constexpr int SX = X + 2, SY = Y + 2, SZ = NDIM == 3 ? Z + 2 : 1;  // P +- 1
-  constexpr int NS = SX * SY * SZ;
-  constexpr int NVX = SX * Y * Z, NVY = X * SY * Z, NVZ = NDIM == 3 ? X * Y * (Z + 2) : 1;
-  constexpr int UI = (NS + NT - 1) / NT, UX = (NVX + NT - 1) / NT, UY = (NVY + NT - 1) / NT;
-  constexpr int UZ = NDIM == 3 ? (NVZ + NT - 1) / NT : 0;
-  __shared__ float sI[NS], sZ[NS], sVx[NVX], sVy[NVY], sVz[NVZ];
+  constexpr int SX = S::SX, SY = S::SY;
+  __shared__ float sI[S::NS], sZ[S::NS], sVx[S::NVX], sVy[S::NVY], sVz[S::NVZ];
   __shared__ float sh[NT / 64];
   __shared__ float sD;
   const int tix = xcd_tile(gridDim.x);
@@ -508,57 +584,7 @@ __global__ __launch_bounds__(NT) void k_advect_lds(const PairDev* __restrict__ p
   const float* __restrict__ Zs = I + N;
   float* __restrict__ Io = stog ? stog + 2 * P.off : nullptr;
   const int x0 = t.a, y0 = t.b, z0 = t.c;
-  // global index of the box point (bx, by, bz) relative to (x0 + ox, ...), clamped
-  auto gidx = [&](int bx, int by, int bz, int ox, int oy, int oz) -> unsigned {
-    const int gx = clampi(x0 + ox + bx, 0, nx - 1), gy = clampi(y0 + oy + by, 0, ny - 1);
-    const int gz = NDIM == 3 ? clampi(z0 + oz + bz, 0, nz - 1) : 0;
-    return (unsigned)((gz * ny + gy) * nx + gx);
-  };
-  {
-    float a[UI], b[UI], cx[UX], cy[UY], cz[UZ > 0 ? UZ : 1];
-#pragma unroll
-    for (int u = 0; u < UI; ++u) {
-      const int j = min((int)threadIdx.x + u * NT, NS - 1);
-      const unsigned g = gidx(j % SX, (j / SX) % SY, j / (SX * SY), -1, -1, -1);
-      a[u] = gld(I, g);
-      b[u] = gld(Zs, g);
-    }
-#pragma unroll
-    for (int u = 0; u < UX; ++u) {
-      const int j = min((int)threadIdx.x + u * NT, NVX - 1);
-      cx[u] = gld(Vx, gidx(j % SX, (j / SX) % Y, j / (SX * Y), -1, 0, 0));
-    }
-#pragma unroll
-    for (int u = 0; u < UY; ++u) {
-      const int j = min((int)threadIdx.x + u * NT, NVY - 1);
-      cy[u] = gld(Vy, gidx(j % X, (j / X) % SY, j / (X * SY), 0, -1, 0));
-    }
-#pragma unroll
-    for (int u = 0; u < UZ; ++u) {
-      const int j = min((int)threadIdx.x + u * NT, NVZ - 1);
-      cz[u] = gld(V, gidx(j % X, (j / X) % Y, j / (X * Y), 0, 0, -1));
-    }
-#pragma unroll
-    for (int u = 0; u < UI; ++u) {
-      const int j = threadIdx.x + u * NT;
-      if (j < NS) { sI[j] = a[u]; sZ[j] = b[u]; }
-    }
-#pragma unroll
-    for (int u = 0; u < UX; ++u) {
-      const int j = threadIdx.x + u * NT;
-      if (j < NVX) sVx[j] = cx[u];
-    }
-#pragma unroll
-    for (int u = 0; u < UY; ++u) {
-      const int j = threadIdx.x + u * NT;
-      if (j < NVY) sVy[j] = cy[u];
-    }
-#pragma unroll
-    for (int u = 0; u < UZ; ++u) {
-      const int j = threadIdx.x + u * NT;
-      if (j < NVZ) sVz[j] = cz[u];
-    }
-  }
+  stage_tile<NDIM>(x0, y0, z0, nx, ny, nz, I, Zs, Vx, Vy, V, sI, sZ, sVx, sVy, sVz);
   __syncthreads();
 
   // velocity, divergence and displacement at the thread's voxels
@@ -1089,6 +1115,86 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   }
 }
 
+// Staged-tile variant of the adjoint epilogue (below): I and z on P +- 1 and
+// the channel of mbar of axis a with a halo along a, staged in LDS with
+// coalesced loads; same arithmetic as k_epilogue.
+template <int NDIM>
+__global__ __launch_bounds__(NT) void k_epilogue_lds(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
+                                                     const float* __restrict__ mbg, const float* __restrict__ stg,
+                                                     float* __restrict__ scg, float* __restrict__ abg, EpiArgs A) {
+  using B = Blk<NDIM>;
+  using S = Stage<NDIM>;
+  constexpr int PPT = B::PPT, SX = S::SX, SY = S::SY, X = S::X, Y = S::Y;
+  __shared__ float sI[S::NS], sZ[S::NS], sMx[S::NVX], sMy[S::NVY], sMz[S::NVZ];
+  const Tile t = tl[xcd_tile(gridDim.x)];
+  const PairDev& P = pd[t.pair];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned N = (unsigned)P.N;
+  const float* __restrict__ MB = mbg + NDIM * P.off;
+  const float* __restrict__ I = stg + 2 * P.off;
+  const float* __restrict__ Z = I + N;
+  float* __restrict__ SI = scg + 2 * P.off;
+  float* __restrict__ SZ = SI + N;
+  const int x0 = t.a, y0 = t.b, z0 = t.c;
+  bool clear = false;
+  if (!A.first) {
+    const float Dn = __uint_as_float(A.dmax[(long long)t.pair * A.T + A.t - 1]);
+    clear = A.force_global || !(Dn < (float)B::HS);
+  }
+  int lq[PPT][3];
+  bool inside[PPT];
+  unsigned idx[PPT];
+  float si[PPT], sz[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    inside[k] = x0 + lx < nx && y0 + ly < ny && z0 + lz < nz;
+    lx = min(lx, nx - 1 - x0); ly = min(ly, ny - 1 - y0); lz = min(lz, nz - 1 - z0);
+    lq[k][0] = lz; lq[k][1] = ly; lq[k][2] = lx;
+    idx[k] = (unsigned)(((z0 + lz) * ny + y0 + ly) * nx + x0 + lx);
+    sz[k] = gld(SZ, idx[k]);
+    si[k] = gld(SI, idx[k]);
+  }
+  stage_tile<NDIM>(x0, y0, z0, nx, ny, nz, I, Z, MB + (NDIM - 1) * N, MB + (NDIM - 2) * N, MB, sI, sZ, sMx, sMy,
+                   sMz);
+  __syncthreads();
+  const int n[3] = {nz, ny, nx};
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int lz = lq[k][0], ly = lq[k][1], lx = lq[k][2];
+    const int q[3] = {z0 + lz, y0 + ly, x0 + lx};
+    const int sq = S::box(lx, ly, lz);
+    const float zc = sZ[sq];
+    float zbar = sz[k], Ibar = si[k];
+#pragma unroll
+    for (int c = 0; c < NDIM; ++c) {
+      const int a = 3 - NDIM + c;  // geometric axis of channel c
+      const int so = a == 2 ? 1 : (a == 1 ? SX : SX * SY);   // box stride along a
+      const float* sm = a == 2 ? sMx : (a == 1 ? sMy : sMz);
+      const int mi = a == 2 ? S::vx(lx, ly, lz) : (a == 1 ? S::vy(lx, ly, lz) : S::vz(lx, ly, lz));
+      const int mo = a == 2 ? 1 : (a == 1 ? X : X * Y);      // stride along a in the channel's array
+      const float m0 = sm[mi];
+      zbar = fmaf(m0, 0.5f * (sI[sq + so] - sI[sq - so]), zbar);
+      const float zmu = sZ[sq + so] * sm[mi + mo], zmd = sZ[sq - so] * sm[mi - mo], zm = zc * m0;
+      const bool lo = q[a] == 0, hi = q[a] == n[a] - 1;
+      Ibar += lo ? -0.5f * (zm + zmu) : (hi ? 0.5f * (zmd + zm) : 0.5f * (zmd - zmu));
+    }
+    if (!inside[k]) continue;
+    if (A.first) {
+      if (P.outG) gst(P.outG, idx[k], fmaf(2.f * P.lam * P.rho, zc, zbar));
+    } else {
+      float* __restrict__ ABo = abg + 2 * P.off;
+      gst(ABo, idx[k], Ibar);
+      gst(ABo, N + idx[k], zbar);
+    }
+    if (clear) {
+      gst(SI, idx[k], 0.f);
+      gst(SZ, idx[k], 0.f);
+    }
+  }
+}
+
 // Transpose of m_c = z D_c I given mbar (already -G vbar, plus the
 // regulariser's term at t = 0):
 //   zbar_t = scatter part + sum_c mbar_c D_c I_t
@@ -1279,11 +1385,11 @@ hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream
 
 hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStream_t s) {
   if (ndim == 2) {
-    if (opt == 0) k_epilogue<2, EPI_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
-    else k_epilogue<2, EPI_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+    if (opt == 0) k_epilogue_lds<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+    else k_epilogue<2, EPI_BATCH[0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
   } else {
-    if (opt == 0) k_epilogue<3, EPI_BATCH[1][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
-    else k_epilogue<3, EPI_BATCH[1][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+    if (opt == 0) k_epilogue_lds<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
+    else k_epilogue<3, EPI_BATCH[1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
   }
   return post();
 }
