@@ -73,7 +73,7 @@ def family_of(kernel_name: str) -> str:
     if "k_xpass" in n:
         return "xpass_gradmul" if "true>" in n else "xpass_plain"
     if "k_spass" in n:
-        mode = n.split("k_spass<")[1].split(">")[0].split(",")[-1].strip()
+        mode = n.split("k_spass<")[1].split(">")[0].split(",")[2].strip()
         return {"0": "spass_mid", "1": "spass_v", "2": "spass_mbar"}[mode]
     if "k_init" in n:
         return "init"
@@ -216,6 +216,98 @@ def cpu_baseline(workload, seconds):
                       f"({used:.1f} s, single-threaded NumPy)"}
 
 
+def copy_rate(nbytes: int, torch, reps: int = 20) -> float:
+    """GB/s of a plain device-to-device copy that reads and writes nbytes in
+    total (the bandwidth a streaming kernel reaches at this working-set size)."""
+    n = max(1, nbytes // 8)
+    a = torch.rand(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return 8.0 * n * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
+
+
+def measure(name, steps, warmup, profile_steps, flags, autotune, torch, api, synthetic, keep_plan=False,
+            fixed=None):
+    """Times `steps` graph replays of cost + dH/dp0 over workload `name`, then
+    one profiled pass for per-kernel durations and the roofline record."""
+    t_gen = time.perf_counter()
+    wl = synthetic.workload(name, p0_kind="realistic")
+    d = wl.pairs[0].ndim
+    voxels = sum(p.size for p in wl.pairs)
+    vsteps = voxels * wl.T
+    print(f"[bench] {name}: {len(wl.pairs)} pairs, {voxels} voxels, T={wl.T} "
+          f"(inputs {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    plan = build_plan(wl, flags, torch, api)
+    tuning = None
+    if fixed is not None:
+        plan.tuning = fixed
+        tuning = plan.tuning
+    elif autotune:
+        t_tune = time.perf_counter()
+        tuning = plan.autotune()
+        print(f"[bench] {name} autotune: choices {tuning} ({time.perf_counter() - t_tune:.1f} s)", file=sys.stderr,
+              flush=True)
+    for _ in range(warmup):
+        plan.grad()
+    torch.cuda.synchronize()
+    secs = time_evals(plan, steps, torch)
+    ms_per_step = 1000.0 * secs / steps
+    value = vsteps * steps / secs
+    costs = plan.out_cost[:, 0].cpu().numpy()
+    assert np.all(np.isfinite(costs)), "non-finite cost"
+    print(f"[bench] {name} fused: {ms_per_step:.3f} ms/eval, {value:.4g} voxel-steps/s", file=sys.stderr, flush=True)
+
+    # per-kernel durations: HIP events around every launch on the launch stream
+    plan.set_profiling(True)
+    plan.reset_stats()
+    for _ in range(profile_steps):
+        plan.grad()
+    stats = plan.kernel_stats()
+    plan.set_profiling(False)
+    kernels = {}
+    for kname, (n, ms) in stats.items():
+        if n == 0:
+            continue
+        bpl = bytes_per_voxel(kname, d) * voxels
+        avg = ms / n
+        kernels[kname] = {"launches_per_eval": n / profile_steps, "avg_us": 1000.0 * avg,
+                          "ms_per_eval": ms / profile_steps,
+                          "algorithmic_GBps": (bpl / (avg / 1000.0)) / 1e9 if avg > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_eval"])
+    dk = kernels[dom]
+    bpl = bytes_per_voxel(dom, d) * voxels
+    achieved = bpl / (dk["avg_us"] * 1e-6) / 1e9
+    copy_gbps = copy_rate(bpl, torch)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(dom, name, None),
+                "algorithmic_bytes_per_launch": bpl, "avg_launch_us": dk["avg_us"],
+                "copy_same_bytes_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps}
+    step_bytes = sum(bytes_per_voxel(k, d) * voxels * v["launches_per_eval"] for k, v in kernels.items())
+    print(f"[bench] {name} dominant kernel {dom}: {dk['avg_us']:.1f} us/launch, {achieved:.0f} GB/s algorithmic "
+          f"(a plain copy of the same bytes: {copy_gbps:.0f} GB/s)", file=sys.stderr, flush=True)
+    out = {"pairs": len(wl.pairs), "voxels": voxels, "T": wl.T, "voxel_steps": vsteps, "value": value,
+           "unit": "voxel-steps/s", "ms_per_eval": ms_per_step, "secs": secs,
+           "pair_evals_per_s": len(wl.pairs) * steps / secs, "steps": steps, "tuning": tuning,
+           "step_algorithmic_GBps": step_bytes / (ms_per_step / 1000.0) / 1e9,
+           "step_hbm_frac": step_bytes / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBPS,
+           "step_bytes": step_bytes, "roofline": roofline, "kernels": kernels}
+    if keep_plan:
+        out["_workload"], out["_plan"] = wl, plan
+    else:
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +322,10 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="extra plan flags (bit mask of SHOOT_*)")
     ap.add_argument("--no-extra", action="store_true", help="skip the full-store and single-pair lines")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tuning", default=None, metavar="C0,C1,...",
+                    help="launch-shape choices to use instead of autotuning (comma-separated 0/1)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the batched 3-D (c5) line among the extras")
+    ap.add_argument("--steps-3d", type=int, default=10, help="timed evaluations of the batched 3-D line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="only run a plain copy of MB MiB (counter calibration) and exit")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -256,59 +352,14 @@ def main():
     import synthetic
     from paper_2106_08817_amd import api
 
-    t_gen = time.perf_counter()
-    wl = synthetic.workload(args.workload, p0_kind="realistic")
-    d = wl.pairs[0].ndim
-    voxels = sum(p.size for p in wl.pairs)
-    vsteps = voxels * wl.T
-    print(f"[bench] {args.workload}: {len(wl.pairs)} pairs, {voxels} voxels, T={wl.T} "
-          f"(inputs {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
-
-    plan = build_plan(wl, args.flags, torch, api)
-    tuning = None
-    if not args.no_autotune:
-        t_tune = time.perf_counter()
-        tuning = plan.autotune()
-        print(f"[bench] autotune: choices {tuning} ({time.perf_counter() - t_tune:.1f} s)", file=sys.stderr,
-              flush=True)
-    for _ in range(args.warmup):
-        plan.grad()
-    torch.cuda.synchronize()
-    secs = time_evals(plan, args.steps, torch)
-    ms_per_step = 1000.0 * secs / args.steps
-    value = vsteps * args.steps / secs
+    fixed = [int(c) for c in args.tuning.split(",")] if args.tuning else None
+    main_run = measure(args.workload, args.steps, args.warmup, args.profile_steps, args.flags,
+                       not args.no_autotune and fixed is None, torch, api, synthetic, keep_plan=True, fixed=fixed)
+    wl, plan = main_run.pop("_workload"), main_run.pop("_plan")
+    voxels, vsteps, value, secs = main_run["voxels"], main_run["voxel_steps"], main_run["value"], main_run["secs"]
+    ms_per_step, kernels, roofline = main_run["ms_per_eval"], main_run["kernels"], main_run["roofline"]
+    tuning, step_bytes = main_run["tuning"], main_run["step_bytes"]
     costs = plan.out_cost[:, 0].cpu().numpy()
-    assert np.all(np.isfinite(costs)), "non-finite cost"
-    print(f"[bench] fused: {ms_per_step:.3f} ms/eval, {value:.4g} voxel-steps/s", file=sys.stderr, flush=True)
-
-    # per-kernel durations: HIP events around every launch on the launch stream
-    plan.set_profiling(True)
-    plan.reset_stats()
-    for _ in range(args.profile_steps):
-        plan.grad()
-    stats = plan.kernel_stats()
-    plan.set_profiling(False)
-    kernels = {}
-    for name, (n, ms) in stats.items():
-        if n == 0:
-            continue
-        per_eval = n / args.profile_steps
-        bpl = bytes_per_voxel(name, d) * voxels
-        avg = ms / n
-        kernels[name] = {"launches_per_eval": per_eval, "avg_us": 1000.0 * avg,
-                         "ms_per_eval": ms / args.profile_steps,
-                         "algorithmic_GBps": (bpl / (avg / 1000.0)) / 1e9 if avg > 0 else None}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_eval"])
-    dk = kernels[dom]
-    bpl = bytes_per_voxel(dom, d) * voxels
-    achieved = bpl / (dk["avg_us"] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, args.workload, None)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": bpl, "avg_launch_us": dk["avg_us"]}
-    step_bytes = sum(bytes_per_voxel(k, d) * voxels * v["launches_per_eval"] for k, v in kernels.items())
-    print(f"[bench] dominant kernel {dom}: {dk['avg_us']:.1f} us/launch, {achieved:.0f} GB/s algorithmic",
-          file=sys.stderr, flush=True)
 
     extra = {}
     if not args.no_extra:
@@ -336,7 +387,14 @@ def main():
                                        "voxel_steps_per_s": v2 * n2 / s2,
                                        "workload": "c2: " + WORKLOADS["c2"]}
             p2.close()
-        print(f"[bench] extra: {json.dumps(extra)}", file=sys.stderr, flush=True)
+        if args.workload != "c5" and not args.no_3d:
+            r5 = measure("c5", args.steps_3d, 2, 1, args.flags, not args.no_autotune, torch, api, synthetic)
+            for key in ("secs", "step_bytes"):
+                r5.pop(key, None)
+            r5["workload"] = "c5: " + WORKLOADS["c5"]
+            extra["batched_3d_c5"] = r5
+        print(f"[bench] extra: {json.dumps({k: v for k, v in extra.items() if k != 'batched_3d_c5'})}",
+              file=sys.stderr, flush=True)
 
     unfused = None
     if not args.no_unfused:
@@ -376,9 +434,9 @@ def main():
                    "voxels": voxels, "T": wl.T, "p0": "realistic (smooth, ~0.3 px per step)",
                    "flags": args.flags, "mode": "batched tile lists, sqrt(T) checkpoints, captured HIP graph",
                    "tuning": tuning},
-        "pair_evals_per_s": len(wl.pairs) * args.steps / secs,
-        "step_algorithmic_GBps": step_bytes / (ms_per_step / 1000.0) / 1e9,
-        "step_hbm_frac": step_bytes / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBPS,
+        "pair_evals_per_s": main_run["pair_evals_per_s"],
+        "step_algorithmic_GBps": main_run["step_algorithmic_GBps"],
+        "step_hbm_frac": main_run["step_hbm_frac"],
         "roofline": roofline,
         "unfused": unfused,
         "cpu_baseline": cpu,
