@@ -185,6 +185,21 @@ shoot_status shoot_cost(shoot_plan plan, void* stream);
 shoot_status shoot_grad_p0(shoot_plan plan, void* stream);
 
 /*
+ * One fixed-step gradient-descent iteration on every pair (the optional
+ * update p0 <- p0 - eta dH/dp0 after the gradient; the paper optimises its
+ * costs by gradient descent, Results). Evaluates cost and dH/dp0 exactly as
+ * shoot_grad_p0 (out_grad and out_cost are required and hold the values at
+ * the p0 of this call), then on the device halves a pair's step eta_i when
+ * its cost rose since the previous call, and writes p0 - eta_i dH/dp0 into
+ * the pair's p0 buffer, which must therefore be writable. With reset != 0
+ * every eta_i starts at eta0 (finite, > 0) and no previous cost is compared;
+ * the first call after shoot_plan_bind must reset (else SHOOT_E_STATE).
+ * Asynchronous and graph-capturable like the other calls; not available on
+ * SHOOT_UNFUSED plans (SHOOT_E_ARG).
+ */
+shoot_status shoot_descend(shoot_plan plan, float eta0, int32_t reset, void* stream);
+
+/*
  * Diagnostics. With profiling enabled, execution calls run eagerly (no graph)
  * with a HIP event pair around every kernel launch on the launch stream, and
  * synchronise the stream before returning; per-kernel launch counts and total

@@ -49,6 +49,7 @@ EXPORTS = {
     "shoot_forward": (c_int32, [c_void_p, c_void_p]),
     "shoot_cost": (c_int32, [c_void_p, c_void_p]),
     "shoot_grad_p0": (c_int32, [c_void_p, c_void_p]),
+    "shoot_descend": (c_int32, [c_void_p, c_float, c_int32, c_void_p]),
     "shoot_plan_set_profiling": (c_int32, [c_void_p, c_int32]),
     "shoot_plan_reset_stats": (c_int32, [c_void_p]),
     "shoot_plan_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_char_p), POINTER(ctypes.c_int64),

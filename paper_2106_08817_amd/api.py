@@ -152,6 +152,16 @@ class Plan:
         """Cost and dH/dp0 of every pair (hand-written discrete adjoint)."""
         self._call(self._lib.shoot_grad_p0, "shoot_grad_p0", stream)
 
+    def descend(self, eta0: float = 1.0, reset: bool = False, stream=None) -> None:
+        """One gradient-descent iteration on every pair's p0 (in place, on the
+        device): cost and dH/dp0 at the current p0, then p0 -= eta_i dH/dp0,
+        with eta_i halved when the pair's cost rose (reset: eta_i = eta0)."""
+        if self._plan is None:
+            raise RuntimeError("plan is closed")
+        with torch.cuda.device(self.device):
+            st = self._lib.shoot_descend(self._plan, float(eta0), 1 if reset else 0, _stream_ptr(stream))
+        _lib.check(st, "shoot_descend")
+
     def autotune(self, stream=None) -> list:
         """Time both options of every launch-shape choice and keep the faster
         ones (bit-identical results); returns the chosen tuning."""
@@ -250,23 +260,14 @@ def shoot_cost(S, J, p0, rho, sigma, lam=0.01, T=10, flags=0):
     return ShootCost.apply(S, J, p0, rho, sigma, lam, T, flags)
 
 
-def gradient_descent(pairs: Sequence[PairSpec], T: int, iters: int, eta: float = 1.0, flags: int = 0,
-                     sync_every: int = 1):
-    """Fixed-step gradient descent on every pair's p0 (updated in place), with
-    the step of a pair halved whenever its cost rises. Returns the plan and the
-    cost history [iters, n_pairs]."""
+def gradient_descent(pairs: Sequence[PairSpec], T: int, iters: int, eta: float = 1.0, flags: int = 0):
+    """Fixed-step gradient descent on every pair's p0 (updated in place on the
+    device by shoot_descend), with the step of a pair halved whenever its cost
+    rises. Returns the plan and the cost history [iters, n_pairs] (the cost at
+    the p0 each iteration started from)."""
     plan = Plan(pairs, T, flags, outputs=("grad", "cost"))
-    n = len(pairs)
-    etas = torch.full((n,), float(eta), dtype=torch.float32, device=plan.device)
-    prev = None
     hist = []
-    for _ in range(iters):
-        plan.grad()
-        H = plan.out_cost[:, 0].clone()
-        if prev is not None:
-            etas = torch.where(H > prev, etas * 0.5, etas)
-        prev = H
-        hist.append(H)
-        for i, ps in enumerate(pairs):
-            ps.p0.sub_(etas[i] * plan.out_grad[i])
+    for it in range(iters):
+        plan.descend(eta, reset=(it == 0))
+        hist.append(plan.out_cost[:, 0].clone())
     return plan, torch.stack(hist) if hist else None

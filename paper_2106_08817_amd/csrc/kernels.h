@@ -59,5 +59,8 @@ hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream
 hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStream_t s);
 hipError_t launch_finalize(int npairs, const PairDev* pd, const float* red_reg, const float* red_ssd,
                            hipStream_t s);
+// Descent step after a gradient: per-pair step control, then p0 -= eta dH/dp0.
+hipError_t launch_descend(int ndim, int npairs, const PairDev* pd, const Tile* tl, int nt, float* eta, float* prev,
+                          int reset, float eta0, hipStream_t s);
 
 }  // namespace shoot

@@ -1305,6 +1305,44 @@ __global__ __launch_bounds__(NT) void k_finalize(const PairDev* __restrict__ pd,
   }
 }
 
+// Fixed-step gradient descent on p0 (the optional update after the
+// gradient): the step of a pair is halved when its cost rose since the
+// previous iteration (on reset the step is eta0 and no cost precedes).
+__global__ __launch_bounds__(NT) void k_descend_eta(const PairDev* __restrict__ pd, int npairs,
+                                                    float* __restrict__ eta, float* __restrict__ prev, int reset,
+                                                    float eta0) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= npairs) return;
+  const float H = pd[i].outCost[0];
+  float e = reset ? eta0 : eta[i];
+  if (!reset && H > prev[i]) e *= 0.5f;
+  eta[i] = e;
+  prev[i] = H;
+}
+
+// p0 <- p0 - eta dH/dp0, in the caller's p0 buffer (the next evaluation copies
+// it into the state afresh).
+template <int NDIM>
+__global__ __launch_bounds__(NT) void k_descend(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
+                                                const float* __restrict__ eta) {
+  using B = Blk<NDIM>;
+  const Tile t = tl[xcd_tile(gridDim.x)];
+  const PairDev& P = pd[t.pair];
+  float* __restrict__ p0 = const_cast<float*>(P.p0);
+  const float* __restrict__ G = P.outG;
+  const float e = eta[t.pair];
+#pragma unroll
+  for (int k = 0; k < B::PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    const int x = t.a + lx, y = t.b + ly, z = t.c + lz;
+    if (x < P.nx && y < P.ny && z < P.nz) {
+      const unsigned idx = (unsigned)((z * P.ny + y) * P.nx + x);
+      gst(p0, idx, fmaf(-e, gld(G, idx), gld(p0, idx)));
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
@@ -1391,6 +1429,14 @@ hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStrea
     if (opt == 0) k_epilogue_lds<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
     else k_epilogue<3, EPI_BATCH[1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
   }
+  return post();
+}
+
+hipError_t launch_descend(int ndim, int npairs, const PairDev* pd, const Tile* tl, int nt, float* eta, float* prev,
+                          int reset, float eta0, hipStream_t s) {
+  k_descend_eta<<<(npairs + NT - 1) / NT, NT, 0, s>>>(pd, npairs, eta, prev, reset, eta0);
+  if (ndim == 2) k_descend<2><<<nt, NT, 0, s>>>(pd, tl, eta);
+  else k_descend<3><<<nt, NT, 0, s>>>(pd, tl, eta);
   return post();
 }
 

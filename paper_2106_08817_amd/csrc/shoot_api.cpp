@@ -40,7 +40,8 @@ constexpr size_t LDS_HARD = 64 * 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-enum Op { OP_FORWARD = 0, OP_COST = 1, OP_GRAD = 2 };
+enum Op { OP_FORWARD = 0, OP_COST = 1, OP_GRAD = 2, OP_DESCEND = 3, OP_DESCEND_RESET = 4, OP_N = 5 };
+bool is_grad(int op) { return op == OP_GRAD || op == OP_DESCEND || op == OP_DESCEND_RESET; }
 
 // One admission wave: a subset of the pairs run together.
 struct Wave {
@@ -52,7 +53,7 @@ struct Wave {
   size_t lds_x[2] = {0, 0}, lds_y[2] = {0, 0}, lds_z[2] = {0, 0};
   // header offsets (bytes from the workspace base)
   size_t o_pd = 0, o_tb = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
-  size_t o_dmax = 0, o_rreg = 0, o_rssd = 0;
+  size_t o_dmax = 0, o_rreg = 0, o_rssd = 0, o_eta = 0, o_prev = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
 };
@@ -64,11 +65,11 @@ struct Fields {  // byte offsets of the field arrays inside the field region
 // Kernel families, for the profiling statistics.
 enum KId {
   KI_FILL, KI_INIT, KI_XPASS_M, KI_XPASS_V, KI_SPASS_MID, KI_SPASS_V, KI_SPASS_MBAR,
-  KI_ADVECT, KI_ADV_ADJ, KI_EPILOGUE, KI_FINALIZE, KI_COUNT
+  KI_ADVECT, KI_ADV_ADJ, KI_EPILOGUE, KI_FINALIZE, KI_DESCEND, KI_COUNT
 };
 const char* const KNAMES[KI_COUNT] = {
     "fill", "init", "xpass_gradmul", "xpass_plain", "spass_mid", "spass_v", "spass_mbar",
-    "advect", "advect_adjoint", "epilogue", "finalize"};
+    "advect", "advect_adjoint", "epilogue", "finalize", "descend"};
 
 // Event pairs around launches; resolved after the stream is synchronised.
 struct Prof {
@@ -136,7 +137,9 @@ struct shoot_plan_s {
   char* ws = nullptr;
   int device = -1;
   hipStream_t cap = nullptr;
-  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t graph[OP_N] = {};
+  float eta0 = 1.f;           // step of the descent after a reset
+  bool descend_ready = false; // the descent's per-pair step state is initialised
   unfused::Plan* uf = nullptr;      // SHOOT_UNFUSED state
   bool profiling = false;
   Prof prof;
@@ -303,6 +306,8 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   w.o_dmax = take(w.pdev.size() * (size_t)p->T * sizeof(unsigned));
   w.o_rreg = take(w.tb.size() * sizeof(float));
   w.o_rssd = take(w.tb.size() * sizeof(float));
+  w.o_eta = take(w.pdev.size() * sizeof(float));
+  w.o_prev = take(w.pdev.size() * sizeof(float));
   w.header_bytes = o - base;
   return o;
 }
@@ -320,7 +325,7 @@ struct Ctx {
   int rb;                 // strided-pass outputs per thread
   int o_adv, o_adj, o_epi;  // load-batch options
   unsigned* dmax;
-  float *rreg, *rssd;
+  float *rreg, *rssd, *eta, *prev;
   float *st, *vs, *u, *u2, *ab, *sc, *vb;
   long long ntot;
   Prof* prof;
@@ -341,6 +346,8 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   c.dmax = (unsigned*)(b + w.o_dmax);
   c.rreg = (float*)(b + w.o_rreg);
   c.rssd = (float*)(b + w.o_rssd);
+  c.eta = (float*)(b + w.o_eta);
+  c.prev = (float*)(b + w.o_prev);
   char* f = b + p->header_total;
   const Fields F = field_layout(p, w.ntot);
   c.st = (float*)(f + F.st); c.vs = (float*)(f + F.vs); c.u = (float*)(f + F.u); c.u2 = (float*)(f + F.u2);
@@ -391,7 +398,7 @@ hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
   a.last = (first_pass && t == T - 1) ? 1 : 0;
   a.red_reg = (first_pass && t == 0) ? c.rreg : nullptr;
   a.red_ssd = (first_pass && t == T - 1) ? c.rssd : nullptr;
-  if (a.last && op == OP_GRAD) { a.ab_out = AB(c, T); a.sc_zero = c.sc; }
+  if (a.last && is_grad(op)) { a.ab_out = AB(c, T); a.sc_zero = c.sc; }
   LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.o_adv, c.ntb, a, c.s));
   return hipSuccess;
 }
@@ -445,9 +452,10 @@ hipError_t run_grad(const Ctx& c) {
   for (int s = nseg - 1; s >= 0; --s) {
     const int t0 = s * k, t1 = std::min(T, t0 + k);
     if (s != nseg - 1) {
-      // restore states t0+1 .. t1-1 and velocities t0 .. t1-1 from checkpoint t0
+      // restore states t0+1 .. t1-1 and velocities t0 .. t1-1 from checkpoint
+      // t0 (the last step needs only its velocity: state t1 is a checkpoint)
       for (int t = t0; t < t1; ++t) {
-        e = fwd_step(c, t, t + 1 < t1, OP_GRAD, false);
+        e = t + 1 < t1 ? fwd_step(c, t, true, OP_GRAD, false) : velocity(c, t);
         if (e != hipSuccess) return e;
       }
     }
@@ -463,8 +471,13 @@ hipError_t enqueue(shoot_plan_s* p, int op, hipStream_t s) {
   for (Wave& w : p->waves) {
     Ctx c = make_ctx(p, w, s);
     c.prof = p->profiling ? &p->prof : nullptr;
-    hipError_t e = (op == OP_GRAD) ? run_grad(c) : run_forward(c, op);
+    hipError_t e = is_grad(op) ? run_grad(c) : run_forward(c, op);
     if (e != hipSuccess) return e;
+    if (op == OP_DESCEND || op == OP_DESCEND_RESET) {
+      const int reset = op == OP_DESCEND_RESET ? 1 : 0;
+      LAUNCH(KI_DESCEND, launch_descend(p->ndim, (int)w.pdev.size(), c.pd, c.tb, c.ntb, c.eta, c.prev, reset,
+                                        p->eta0, c.s));
+    }
   }
   return hipSuccess;
 }
@@ -481,7 +494,8 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
     const shoot_pair& q = p->pairs[i];
     if (op != OP_FORWARD && !q.target) return fail(SHOOT_E_ARG, "target is NULL (pair " + std::to_string(i) + ")");
     if (op == OP_COST && !q.out_cost) return fail(SHOOT_E_ARG, "out_cost is NULL (pair " + std::to_string(i) + ")");
-    if (op == OP_GRAD && !q.out_grad) return fail(SHOOT_E_ARG, "out_grad is NULL (pair " + std::to_string(i) + ")");
+    if (is_grad(op) && !q.out_grad) return fail(SHOOT_E_ARG, "out_grad is NULL (pair " + std::to_string(i) + ")");
+    if (op >= OP_DESCEND && !q.out_cost) return fail(SHOOT_E_ARG, "out_cost is NULL (pair " + std::to_string(i) + ")");
   }
   int dev = -1;
   HIPCHK(hipGetDevice(&dev));
@@ -651,6 +665,7 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
   if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   p->device = dev;
   p->ws = (char*)workspace;
+  p->descend_ready = false;
   hipStream_t s = (hipStream_t)stream;
   if (p->uf) {
     hipError_t e = unfused::bind(p->uf, p->ws, s);
@@ -734,6 +749,24 @@ shoot_status shoot_plan_set_tuning(shoot_plan p, const int32_t* choices) {
 shoot_status shoot_forward(shoot_plan p, void* stream) { return execute(p, OP_FORWARD, stream); }
 shoot_status shoot_cost(shoot_plan p, void* stream) { return execute(p, OP_COST, stream); }
 shoot_status shoot_grad_p0(shoot_plan p, void* stream) { return execute(p, OP_GRAD, stream); }
+
+shoot_status shoot_descend(shoot_plan p, float eta0, int32_t reset, void* stream) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (p->uf) return fail(SHOOT_E_ARG, "descent is not available on the unfused path");
+  if (reset) {
+    if (!(eta0 > 0.f) || !std::isfinite(eta0)) return fail(SHOOT_E_ARG, "eta0 must be finite and > 0");
+    if (eta0 != p->eta0 && p->graph[OP_DESCEND_RESET]) {
+      (void)hipGraphExecDestroy(p->graph[OP_DESCEND_RESET]);
+      p->graph[OP_DESCEND_RESET] = nullptr;
+    }
+    p->eta0 = eta0;
+  } else if (!p->descend_ready) {
+    return fail(SHOOT_E_STATE, "the first shoot_descend call after a bind must reset");
+  }
+  shoot_status st = execute(p, reset ? OP_DESCEND_RESET : OP_DESCEND, stream);
+  if (st == SHOOT_OK) p->descend_ready = true;
+  return st;
+}
 
 shoot_status shoot_plan_set_profiling(shoot_plan p, int32_t enable) {
   if (!p) return fail(SHOOT_E_ARG, "plan is NULL");

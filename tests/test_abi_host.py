@@ -145,3 +145,17 @@ def test_tuning_choices_host_side():
     # autotune needs a bound workspace
     assert lib.shoot_autotune(h, None) == _lib.SHOOT_E_STATE
     lib.shoot_plan_destroy(h)
+
+
+def test_descend_requires_bind_and_validates_step():
+    lib = _lib.load()
+    st, h = create([pair(shape=(40, 52))], T=4)
+    assert st == _lib.SHOOT_OK
+    assert lib.shoot_descend(h, 0.0, 1, None) == _lib.SHOOT_E_ARG       # eta0 must be > 0
+    assert lib.shoot_descend(h, float("nan"), 1, None) == _lib.SHOOT_E_ARG
+    assert lib.shoot_descend(h, 1.0, 0, None) == _lib.SHOOT_E_STATE     # no reset yet
+    assert lib.shoot_descend(h, 1.0, 1, None) == _lib.SHOOT_E_STATE     # not bound to a workspace
+    lib.shoot_plan_destroy(h)
+    st, h = create([pair(shape=(40, 52))], T=4, flags=_lib.SHOOT_UNFUSED)
+    assert lib.shoot_descend(h, 1.0, 1, None) == _lib.SHOOT_E_ARG
+    lib.shoot_plan_destroy(h)
