@@ -20,6 +20,9 @@ Parity status of each function (what pins it; tests/test_oracle_*.py):
 * cost_terms, cost_and_grad, step_adjoint: closed form at T = 1, central
   finite differences on 16x16 (and 3-D) inputs, autograd of an independent
   torch float64 program.
+* deformation: identity at zero momentum, the clamped foot in closed form at
+  T = 1, a component that stays the identity when nothing moves along its
+  axis, values within the grid.
 * energy: diagnostic only, parity unpinned (the paper gives no numbers).
 * gradient_descent: parity unpinned (driver; its steps are pinned above).
 """
@@ -30,6 +33,7 @@ from .shooting import (  # noqa: F401
     cost,
     cost_and_grad,
     cost_terms,
+    deformation,
     diff,
     diff_T,
     divergence,

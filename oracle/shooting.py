@@ -263,6 +263,29 @@ def shoot(S, p0, rho: float, sigma: float, T: int) -> Trajectory:
     return Trajectory(Is, zs, vs)
 
 
+def deformation(S, p0, rho: float, sigma: float, T: int, traj: Trajectory = None) -> np.ndarray:
+    """Deformation map of the shot, psi_T (the deformation grids of the Results
+    section, obtained by integrating over every v_t; the flow of Methods,
+    d phi / dt = v o phi, discretised semi-Lagrangianly): psi_0 = Id and
+    psi_{t+1} = psi_t o (Id - dt v_t), i.e. every component of psi_t is
+    re-interpolated at the feet of step t with the clamped multilinear weights
+    that move I and z. psi_T maps the arrival grid back into the source, so for
+    rho = 0, I_T ~ S o psi_T. Returns [d, *shape] in grid coordinates
+    (component a along array axis a)."""
+    if traj is None:
+        traj = shoot(S, p0, rho, sigma, T)
+    shape = np.shape(S)
+    d = len(shape)
+    dt = 1.0 / T
+    q = grid_coords(shape)
+    psi = q.copy()
+    for t in range(T):
+        v = traj.v[t]
+        ft = feet(np.stack([q[a] - dt * _as64(v[a]) for a in range(d)]), shape)
+        psi = np.stack([interp(psi[a], ft) for a in range(d)])
+    return psi
+
+
 def cost_terms(S, J, p0, rho: float, sigma: float, lam: float, T: int, traj: Trajectory = None):
     """(H, data, reg) of the inexact matching cost (Methods, Eq. 4):
     H = 1/2 ||I_1 - J||^2 + lambda (||v0||_V^2 + rho ||z0||^2) with
