@@ -55,6 +55,8 @@ def bytes_per_voxel(name: str, d: int) -> int:
         "advect_adjoint": (d + 2 + 2) + (2 + d),  # read v, I, z, Ibar', zbar'; write Interp^T parts, vbar
         "epilogue": (d + 2 + 2) + 2,     # read mbar, I, z, Interp^T parts; write Ibar, zbar
         "init": 4,
+        "deform": 3 * d,                 # read v, psi; write psi
+        "descend": 3,                    # read p0, dH/dp0; write p0
         "fill": 0,
         "finalize": 0,
     }
@@ -77,6 +79,10 @@ def family_of(kernel_name: str) -> str:
         return {"0": "spass_mid", "1": "spass_v", "2": "spass_mbar"}[mode]
     if "k_init" in n:
         return "init"
+    if "k_deform" in n:
+        return "deform"
+    if "k_descend" in n:
+        return "descend"
     if "k_finalize" in n:
         return "finalize"
     if "k_fill_u32" in n:
@@ -236,6 +242,47 @@ def copy_rate(nbytes: int, torch, reps: int = 20) -> float:
     return 8.0 * n * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
 
 
+def forward_deformation(wl, steps, warmup, torch, api):
+    """shoot_forward over the workload with and without the deformation map
+    psi_T, and the deformation kernel's launch duration and bandwidth."""
+    def plan_for(outs):
+        specs = [api.PairSpec(torch.from_numpy(p.source).cuda(), torch.from_numpy(p.p0).cuda(), p.rho, p.sigma,
+                              p.lam, torch.from_numpy(p.target).cuda()) for p in wl.pairs]
+        return api.Plan(specs, wl.T, 0, outputs=outs)
+
+    def timed(plan):
+        for _ in range(warmup):
+            plan.forward()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.forward()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    d = wl.pairs[0].ndim
+    voxels = sum(p.size for p in wl.pairs)
+    base = plan_for(("image", "momentum", "cost"))
+    ms0 = timed(base)
+    base.close()
+    plan = plan_for(("image", "momentum", "cost", "deformation"))
+    ms1 = timed(plan)
+    plan.set_profiling(True)
+    plan.reset_stats()
+    plan.forward()
+    n, ms = plan.kernel_stats()["deform"]
+    plan.close()
+    avg_us = 1000.0 * ms / n
+    return {"forward_ms": ms0, "forward_with_deformation_ms": ms1, "deform_launches": n,
+            "deform_avg_us": avg_us,
+            "deform_algorithmic_GBps": bytes_per_voxel("deform", d) * voxels / (avg_us * 1e-6) / 1e9,
+            "note": "psi_T: psi_0 = Id, psi_{t+1} = psi_t o (Id - dt v_t), one extra kernel per forward step"}
+
+
 def measure(name, steps, warmup, profile_steps, flags, autotune, torch, api, synthetic, keep_plan=False,
             fixed=None):
     """Times `steps` graph replays of cost + dH/dp0 over workload `name`, then
@@ -387,6 +434,7 @@ def main():
                                        "voxel_steps_per_s": v2 * n2 / s2,
                                        "workload": "c2: " + WORKLOADS["c2"]}
             p2.close()
+        extra["forward_deformation"] = forward_deformation(wl, args.steps, args.warmup, torch, api)
         if args.workload != "c5" and not args.no_3d:
             r5 = measure("c5", args.steps_3d, 2, 1, args.flags, not args.no_autotune, torch, api, synthetic)
             for key in ("secs", "step_bytes"):

@@ -79,6 +79,13 @@ typedef enum shoot_status {
  *   out_cost     [3]  (H, 1/2||I_T-J||^2, lambda(<m0,Gm0> + rho||p0||^2))
  *                     (shoot_cost, shoot_grad_p0, and shoot_forward when
  *                     target is given)
+ *   out_deformation [ndim][N]  psi_T, the deformation map of the shot
+ *                     (shoot_forward): psi_0 = Id, psi_{t+1} = psi_t o
+ *                     (Id - dt v_t) with the scheme's clamped multilinear
+ *                     weights, so that S o psi_T ~ I_T for rho = 0 (the
+ *                     deformation grids of the Results section; the flow of
+ *                     Methods integrated semi-Lagrangianly). Component a is
+ *                     the grid coordinate along array axis a.
  * rho >= 0 weighs the intensity residual; sigma > 0 is the kernel width in
  * pixels (sigma < 32/3, i.e. radius floor(3 sigma) <= 31); lambda >= 0 weighs
  * the regulariser.
@@ -96,6 +103,7 @@ typedef struct shoot_pair {
   float* out_momentum;
   float* out_grad;
   float* out_cost;
+  float* out_deformation;
 } shoot_pair;
 
 typedef struct shoot_plan_s* shoot_plan;
@@ -169,7 +177,8 @@ shoot_status shoot_plan_set_tuning(shoot_plan plan, const int32_t* choices);
 
 /*
  * Shoot every pair: writes out_image (I_T) and out_momentum (z_T) when not
- * NULL, and out_cost when both target and out_cost are given.
+ * NULL, out_cost when both target and out_cost are given, and
+ * out_deformation (psi_T) when not NULL.
  */
 shoot_status shoot_forward(shoot_plan plan, void* stream);
 

@@ -74,6 +74,7 @@ class ShootPair(ctypes.Structure):
         ("out_momentum", c_void_p),
         ("out_grad", c_void_p),
         ("out_cost", c_void_p),
+        ("out_deformation", c_void_p),
     ]
 
 

@@ -62,8 +62,9 @@ class Plan:
 
     Output tensors are allocated here and stay fixed (captured graphs replay
     their addresses): ``out_image``, ``out_momentum``, ``out_grad`` (lists,
-    one tensor per pair) and ``out_cost`` (tensor [n_pairs, 3] =
-    (H, data, reg)). Input tensors must stay alive and in place; their
+    one tensor per pair), ``out_cost`` (tensor [n_pairs, 3] =
+    (H, data, reg)) and, when "deformation" is among the outputs,
+    ``out_deformation`` (list of [ndim, *shape] tensors, psi_T of forward()). Input tensors must stay alive and in place; their
     contents may change between calls (e.g. p0 updated in place).
     """
 
@@ -83,7 +84,7 @@ class Plan:
         outs = set(outputs)
         with torch.cuda.device(device):
             self.out_cost = torch.zeros((n, 3), dtype=torch.float32, device=device) if "cost" in outs else None
-            self.out_image, self.out_momentum, self.out_grad = [], [], []
+            self.out_image, self.out_momentum, self.out_grad, self.out_deformation = [], [], [], []
             arr = (_lib.ShootPair * n)()
             for i, ps in enumerate(self.pairs):
                 shp = tuple(ps.image.shape)
@@ -96,6 +97,9 @@ class Plan:
                 oi = torch.empty_like(ps.image) if "image" in outs else None
                 om = torch.empty_like(ps.image) if "momentum" in outs else None
                 og = torch.empty_like(ps.image) if "grad" in outs else None
+                od = (torch.empty((len(shp),) + shp, dtype=torch.float32, device=device)
+                      if "deformation" in outs else None)
+                self.out_deformation.append(od)
                 self.out_image.append(oi)
                 self.out_momentum.append(om)
                 self.out_grad.append(og)
@@ -113,6 +117,7 @@ class Plan:
                 d.out_momentum = om.data_ptr() if om is not None else None
                 d.out_grad = og.data_ptr() if og is not None else None
                 d.out_cost = (self.out_cost.data_ptr() + 12 * i) if self.out_cost is not None else None
+                d.out_deformation = od.data_ptr() if od is not None else None
             self._desc = arr
             handle = ctypes.c_void_p()
             _lib.check(self._lib.shoot_plan_create(ctypes.cast(arr, ctypes.c_void_p), n, self.T, self.flags,

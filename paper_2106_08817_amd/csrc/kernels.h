@@ -59,6 +59,10 @@ hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream
 hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStream_t s);
 hipError_t launch_finalize(int npairs, const PairDev* pd, const float* red_reg, const float* red_ssd,
                            hipStream_t s);
+// Deformation map, one step: psi_out = psi_in o (Id - dt v) (psi_in null: the
+// identity; psi_out null: the pairs' outD).
+hipError_t launch_deform(int ndim, const PairDev* pd, const Tile* tl, int nt, const float* V, const float* psi_in,
+                         float* psi_out, hipStream_t s);
 // Descent step after a gradient: per-pair step control, then p0 -= eta dH/dp0.
 hipError_t launch_descend(int ndim, int npairs, const PairDev* pd, const Tile* tl, int nt, float* eta, float* prev,
                           int reset, float eta0, hipStream_t s);

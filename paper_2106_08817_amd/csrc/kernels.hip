@@ -1305,6 +1305,66 @@ __global__ __launch_bounds__(NT) void k_finalize(const PairDev* __restrict__ pd,
   }
 }
 
+// One step of the deformation map psi_{t+1} = psi_t o (Id - dt v_t): every
+// component is re-interpolated at the step's feet with the weights that move
+// I and z (psi_0 = Id: the corner values are the corners' coordinates). The
+// result goes to psi_out, or at the last step to each pair's outD.
+template <int NDIM>
+__global__ __launch_bounds__(NT) void k_deform(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
+                                               const float* __restrict__ Vg, const float* __restrict__ psi_in,
+                                               float* __restrict__ psi_out) {
+  using B = Blk<NDIM>;
+  constexpr int NC = NDIM == 3 ? 8 : 4;
+  const Tile t = tl[xcd_tile(gridDim.x)];
+  const PairDev& P = pd[t.pair];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const unsigned N = (unsigned)P.N;
+  const unsigned sxy = (unsigned)(nx * ny);
+  const float dt = P.dt;
+  const float* __restrict__ V = Vg + NDIM * P.off;
+  const float* __restrict__ Pin = psi_in ? psi_in + NDIM * P.off : nullptr;
+  float* __restrict__ Pout = psi_out ? psi_out + NDIM * P.off : P.outD;
+  if (!Pout) return;  // this pair wants no deformation map
+#pragma unroll
+  for (int k = 0; k < B::PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    const bool inside = t.a + lx < nx && t.b + ly < ny && t.c + lz < nz;
+    const int qx = min(t.a + lx, nx - 1), qy = min(t.b + ly, ny - 1), qz = min(t.c + lz, nz - 1);
+    const unsigned idx = (unsigned)((qz * ny + qy) * nx + qx);
+    Axis ax[3];
+    ax[2] = foot_axis(qx, -dt * gld(V, (NDIM - 1) * N + idx), nx);
+    ax[1] = foot_axis(qy, -dt * gld(V, (NDIM - 2) * N + idx), ny);
+    if (NDIM == 3) {
+      ax[0] = foot_axis(qz, -dt * gld(V, idx), nz);
+    } else {
+      ax[0].i = 0; ax[0].f = 0.f; ax[0].live = 0.f;
+    }
+    const unsigned c0 = (unsigned)(ax[0].i * (int)sxy + ax[1].i * nx + ax[2].i);
+    const float fr[3] = {ax[0].f, ax[1].f, ax[2].f};
+    float out[NDIM];
+#pragma unroll
+    for (int c = 0; c < NDIM; ++c) {
+      const int a = 3 - NDIM + c;  // geometric axis of component c
+      float cv[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int b[3] = {j >> 2, (j >> 1) & 1, j & 1};
+        if (Pin) {
+          cv[j] = gld(Pin, c * N + c0 + (unsigned)b[0] * sxy + (unsigned)(b[1] * nx + b[2]));
+        } else {
+          cv[j] = (float)(ax[a].i + b[a]);
+        }
+      }
+      out[c] = mlerp<NDIM>(cv, fr);
+    }
+    if (inside) {
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) gst(Pout, c * N + idx, out[c]);
+    }
+  }
+}
+
 // Fixed-step gradient descent on p0 (the optional update after the
 // gradient): the step of a pair is halved when its cost rose since the
 // previous iteration (on reset the step is eta0 and no cost precedes).
@@ -1429,6 +1489,13 @@ hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStrea
     if (opt == 0) k_epilogue_lds<3><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
     else k_epilogue<3, EPI_BATCH[1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.mb, a.st, a.sc, a.ab_out, a);
   }
+  return post();
+}
+
+hipError_t launch_deform(int ndim, const PairDev* pd, const Tile* tl, int nt, const float* V, const float* psi_in,
+                         float* psi_out, hipStream_t s) {
+  if (ndim == 2) k_deform<2><<<nt, NT, 0, s>>>(pd, tl, V, psi_in, psi_out);
+  else k_deform<3><<<nt, NT, 0, s>>>(pd, tl, V, psi_in, psi_out);
   return post();
 }
 

@@ -59,17 +59,17 @@ struct Wave {
 };
 
 struct Fields {  // byte offsets of the field arrays inside the field region
-  size_t st, vs, u, u2, ab, sc, vb, end;
+  size_t st, vs, u, u2, ab, sc, vb, psi, end;
 };
 
 // Kernel families, for the profiling statistics.
 enum KId {
   KI_FILL, KI_INIT, KI_XPASS_M, KI_XPASS_V, KI_SPASS_MID, KI_SPASS_V, KI_SPASS_MBAR,
-  KI_ADVECT, KI_ADV_ADJ, KI_EPILOGUE, KI_FINALIZE, KI_DESCEND, KI_COUNT
+  KI_ADVECT, KI_ADV_ADJ, KI_EPILOGUE, KI_FINALIZE, KI_DESCEND, KI_DEFORM, KI_COUNT
 };
 const char* const KNAMES[KI_COUNT] = {
     "fill", "init", "xpass_gradmul", "xpass_plain", "spass_mid", "spass_v", "spass_mbar",
-    "advect", "advect_adjoint", "epilogue", "finalize", "descend"};
+    "advect", "advect_adjoint", "epilogue", "finalize", "descend", "deform"};
 
 // Event pairs around launches; resolved after the stream is synchronised.
 struct Prof {
@@ -144,6 +144,7 @@ struct shoot_plan_s {
   bool profiling = false;
   Prof prof;
   int tune[TUNE_N] = {0, 0, 0, 0, 0};
+  bool has_def = false;        // some pair asks for its deformation map
 };
 
 namespace {
@@ -162,6 +163,7 @@ Fields field_layout(const shoot_plan_s* p, long long ntot) {
   F.ab = o; o = align_up(o + 2 * 2 * ntot * f, ALIGN);
   F.sc = o; o = align_up(o + 2 * ntot * f, ALIGN);
   F.vb = o; o = align_up(o + d * ntot * f, ALIGN);
+  F.psi = o; o = align_up(o + (p->has_def ? 2 * d * ntot * f : 0), ALIGN);
   F.end = o;
   return F;
 }
@@ -242,6 +244,7 @@ void build_wave(shoot_plan_s* p, Wave& w) {
     P.dt = (float)(1.0 / (double)p->T);
     P.S = q.image; P.J = q.target; P.p0 = q.p0;
     P.outI = q.out_image; P.outZ = q.out_momentum; P.outG = q.out_grad; P.outCost = q.out_cost;
+    P.outD = q.out_deformation;
     fill_taps(P, q.sigma);
     const int pi = (int)li;
     // block tiles (init, advect, adjoint, epilogue); cost partials are per block tile
@@ -326,7 +329,7 @@ struct Ctx {
   int o_adv, o_adj, o_epi;  // load-batch options
   unsigned* dmax;
   float *rreg, *rssd, *eta, *prev;
-  float *st, *vs, *u, *u2, *ab, *sc, *vb;
+  float *st, *vs, *u, *u2, *ab, *sc, *vb, *psi;
   long long ntot;
   Prof* prof;
 };
@@ -352,6 +355,7 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   const Fields F = field_layout(p, w.ntot);
   c.st = (float*)(f + F.st); c.vs = (float*)(f + F.vs); c.u = (float*)(f + F.u); c.u2 = (float*)(f + F.u2);
   c.ab = (float*)(f + F.ab); c.sc = (float*)(f + F.sc); c.vb = (float*)(f + F.vb);
+  c.psi = (float*)(f + F.psi);
   c.ntot = w.ntot;
   return c;
 }
@@ -407,9 +411,17 @@ hipError_t run_forward(const Ctx& c, int op) {
   const int T = c.p->T;
   LAUNCH(KI_FILL, launch_fill_u32(c.dmax, (long long)c.w->pdev.size() * T, 0u, c.s));
   LAUNCH(KI_INIT, launch_init(c.p->ndim, c.pd, c.tb, c.ntb, ST(c, 0), c.s));
+  const bool def = op == OP_FORWARD && c.p->has_def;
+  const size_t psz = (size_t)c.p->ndim * c.ntot;
   for (int t = 0; t < T; ++t) {
     hipError_t e = fwd_step(c, t, true, op, true);
     if (e != hipSuccess) return e;
+    if (def) {
+      // psi_{t+1} = psi_t o (Id - dt v_t); psi_0 = Id, psi_T to the outputs
+      const float* pin = t == 0 ? nullptr : c.psi + (size_t)(t & 1) * psz;
+      float* pout = t == T - 1 ? nullptr : c.psi + (size_t)((t + 1) & 1) * psz;
+      LAUNCH(KI_DEFORM, launch_deform(c.p->ndim, c.pd, c.tb, c.ntb, VS(c, t), pin, pout, c.s));
+    }
   }
   LAUNCH(KI_FINALIZE, launch_finalize((int)c.w->pdev.size(), c.pd, c.rreg, c.rssd, c.s));
   return hipSuccess;
@@ -570,6 +582,8 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
   p->flags = flags;
   p->budget = budget_bytes;
   p->pairs.assign(pairs, pairs + n_pairs);
+  for (int i = 0; i < n_pairs; ++i)
+    if (pairs[i].out_deformation) p->has_def = true;
   p->k = std::max(1, (int)std::ceil(std::sqrt((double)T) - 1e-9));
   while ((long long)p->k * p->k < T) ++p->k;
   p->nck = (T + p->k - 1) / p->k;

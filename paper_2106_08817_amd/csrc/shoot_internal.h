@@ -68,7 +68,7 @@ struct alignas(16) PairDev {
   float* outZ;
   float* outG;
   float* outCost;
-  long long reserved_;
+  float* outD;    // deformation map psi_T [NDIM][N], or null
   float w[WPAD];  // padded taps (see WPAD)
 };
 static_assert(sizeof(long long) == 8 && sizeof(void*) == 8, "LP64 expected");
