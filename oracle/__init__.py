@@ -25,6 +25,8 @@ Parity status of each function (what pins it; tests/test_oracle_*.py):
   axis, values within the grid.
 * energy: diagnostic only, parity unpinned (the paper gives no numbers).
 * gradient_descent: parity unpinned (driver; its steps are pinned above).
+* lbfgs (oracle/lbfgs.py): two-loop recursion against the explicit BFGS
+  inverse-Hessian product; convergence on a strictly convex quadratic.
 """
 from .shooting import (  # noqa: F401
     Feet,
@@ -54,3 +56,4 @@ from .shooting import (  # noqa: F401
     step_given_v,
     velocity,
 )
+from .lbfgs import lbfgs, minimize as lbfgs_minimize, two_loop  # noqa: F401,E402
