@@ -242,6 +242,29 @@ def copy_rate(nbytes: int, torch, reps: int = 20) -> float:
     return 8.0 * n * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
 
 
+def lbfgs_rate(wl, iters, torch, api):
+    """Wall time of batched L-BFGS iterations over the workload (every pair at
+    once; each iteration evaluates cost + gradient once per line-search trial
+    and synchronises for the per-pair step decisions)."""
+    specs = [api.PairSpec(torch.from_numpy(p.source).cuda(), torch.from_numpy(p.p0).cuda(), p.rho, p.sigma,
+                          p.lam, torch.from_numpy(p.target).cuda()) for p in wl.pairs]
+    plan = api.Plan(specs, wl.T, 0, outputs=("grad", "cost"))
+    opt = api.LBFGS(plan)
+    c0, _ = opt.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    for _ in range(iters):
+        c, e = opt.step()
+        evals += e
+    secs = time.perf_counter() - t0
+    cost_now = plan.out_cost[:, 0].double().sum().item()
+    opt.close()
+    plan.close()
+    return {"ms_per_iteration": 1000.0 * secs / iters, "evaluations_per_iteration": evals / iters,
+            "summed_cost_first": float(sum(c0)), "summed_cost_after": cost_now, "iterations": iters + 1}
+
+
 def forward_deformation(wl, steps, warmup, torch, api):
     """shoot_forward over the workload with and without the deformation map
     psi_T, and the deformation kernel's launch duration and bandwidth."""
@@ -435,6 +458,7 @@ def main():
                                        "workload": "c2: " + WORKLOADS["c2"]}
             p2.close()
         extra["forward_deformation"] = forward_deformation(wl, args.steps, args.warmup, torch, api)
+        extra["lbfgs"] = lbfgs_rate(wl, 4, torch, api)
         if args.workload != "c5" and not args.no_3d:
             r5 = measure("c5", args.steps_3d, 2, 1, args.flags, not args.no_autotune, torch, api, synthetic)
             for key in ("secs", "step_bytes"):

@@ -208,6 +208,42 @@ shoot_status shoot_grad_p0(shoot_plan plan, void* stream);
  */
 shoot_status shoot_descend(shoot_plan plan, float eta0, int32_t reset, void* stream);
 
+/* ------------------------------------------------------------------ L-BFGS
+ * Batched L-BFGS on every pair's p0 over a bound plan (the paper's
+ * alternative to gradient descent for minimising H, Results): the
+ * limited-memory BFGS two-loop recursion and Armijo backtracking, per pair,
+ * with these conventions: at most m stored pairs (s, y), a new one after
+ * every accepted step with rho = 1/(s.y) if s.y > 0 else 0; initial inverse
+ * Hessian gamma Id with gamma = s.y / y.y of the newest pair (1/||g|| at the
+ * start and after a failed search); d = -H g, or -g/||g|| when g.d >= 0;
+ * steps t = 1, 1/2, ... for at most `trials` evaluations, accepting
+ * H(x + t d) <= H(x) + c1 t g.d; a pair whose search fails stays at x and
+ * forgets its history. Vector work runs on the device; every cost and
+ * gradient comes from shoot_grad_p0 on the plan.
+ *
+ * The plan must be created with target, out_grad and out_cost for every pair
+ * (SHOOT_E_ARG otherwise), stay bound and outlive the optimiser; p0 buffers
+ * are overwritten with the iterates. The optimiser owns host memory only; its
+ * device workspace (shoot_lbfgs_workspace_bytes, 256-byte aligned) belongs to
+ * the caller, holds (5 + 2m) floats per voxel, and must stay in place from
+ * bind to destroy. Errors are reported through shoot_last_error.
+ */
+typedef struct shoot_lbfgs_s* shoot_lbfgs;
+
+/* m in [1, 64], c1 in (0, 1), trials in [1, 64]. Host-only. */
+shoot_status shoot_lbfgs_create(shoot_plan plan, int32_t m, float c1, int32_t trials, shoot_lbfgs* out);
+shoot_status shoot_lbfgs_workspace_bytes(shoot_lbfgs opt, size_t* bytes);
+/* Attaches the workspace and (re)starts the iteration at the current p0
+ * (synchronises `stream`). */
+shoot_status shoot_lbfgs_bind(shoot_lbfgs opt, void* workspace, size_t bytes, void* stream);
+/* One iteration for every pair (synchronises `stream`); on return p0 holds the
+ * new iterate and the plan's out_grad / out_cost its gradient and cost. */
+shoot_status shoot_lbfgs_step(shoot_lbfgs opt, void* stream);
+/* The cost of every pair at the start of the last step (host array of n
+ * doubles, may be NULL) and the number of gradient evaluations it used. */
+shoot_status shoot_lbfgs_last_step(shoot_lbfgs opt, double* cost_at_start, int32_t* evaluations);
+shoot_status shoot_lbfgs_destroy(shoot_lbfgs opt);
+
 /*
  * Diagnostics. With profiling enabled, execution calls run eagerly (no graph)
  * with a HIP event pair around every kernel launch on the launch stream, and

@@ -6,10 +6,12 @@ from .api import (  # noqa: F401
     SHOOT_FULL_STORE,
     SHOOT_NO_GRAPH,
     SHOOT_UNFUSED,
+    LBFGS,
     PairSpec,
     Plan,
     ShootCost,
     gradient_descent,
+    lbfgs,
     shoot_cost,
 )
 from ._lib import ShootError, load  # noqa: F401

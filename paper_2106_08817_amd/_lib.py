@@ -50,6 +50,12 @@ EXPORTS = {
     "shoot_cost": (c_int32, [c_void_p, c_void_p]),
     "shoot_grad_p0": (c_int32, [c_void_p, c_void_p]),
     "shoot_descend": (c_int32, [c_void_p, c_float, c_int32, c_void_p]),
+    "shoot_lbfgs_create": (c_int32, [c_void_p, c_int32, c_float, c_int32, POINTER(c_void_p)]),
+    "shoot_lbfgs_workspace_bytes": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "shoot_lbfgs_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "shoot_lbfgs_step": (c_int32, [c_void_p, c_void_p]),
+    "shoot_lbfgs_last_step": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(c_int32)]),
+    "shoot_lbfgs_destroy": (c_int32, [c_void_p]),
     "shoot_plan_set_profiling": (c_int32, [c_void_p, c_int32]),
     "shoot_plan_reset_stats": (c_int32, [c_void_p]),
     "shoot_plan_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_char_p), POINTER(ctypes.c_int64),

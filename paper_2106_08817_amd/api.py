@@ -223,6 +223,68 @@ class Plan:
             pass
 
 
+class LBFGS:
+    """Batched L-BFGS on the p0 of every pair of a plan (shoot_lbfgs_*): the
+    plan needs "grad" and "cost" outputs and every pair a target; p0 tensors
+    are overwritten with the iterates."""
+
+    def __init__(self, plan: Plan, m: int = 5, c1: float = 1e-4, trials: int = 8, stream=None):
+        self._lib = plan._lib
+        self.plan = plan
+        self._opt = None
+        h = ctypes.c_void_p()
+        _lib.check(self._lib.shoot_lbfgs_create(plan._plan, int(m), float(c1), int(trials), ctypes.byref(h)),
+                   "shoot_lbfgs_create")
+        self._opt = h
+        nb = ctypes.c_size_t()
+        _lib.check(self._lib.shoot_lbfgs_workspace_bytes(self._opt, ctypes.byref(nb)), "shoot_lbfgs_workspace_bytes")
+        with torch.cuda.device(plan.device):
+            raw = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=plan.device)
+            shift = (-raw.data_ptr()) % 256
+            self._raw = raw
+            self.workspace = raw[shift:shift + int(nb.value)]
+            _lib.check(self._lib.shoot_lbfgs_bind(self._opt, self.workspace.data_ptr(), int(nb.value),
+                                                  _stream_ptr(stream)), "shoot_lbfgs_bind")
+
+    def step(self, stream=None):
+        """One iteration for every pair; returns (cost at the start of the
+        step per pair, gradient evaluations used)."""
+        with torch.cuda.device(self.plan.device):
+            _lib.check(self._lib.shoot_lbfgs_step(self._opt, _stream_ptr(stream)), "shoot_lbfgs_step")
+        n = len(self.plan.pairs)
+        costs = (ctypes.c_double * n)()
+        ev = ctypes.c_int32()
+        _lib.check(self._lib.shoot_lbfgs_last_step(self._opt, costs, ctypes.byref(ev)), "shoot_lbfgs_last_step")
+        return [float(c) for c in costs], int(ev.value)
+
+    def close(self):
+        if self._opt is not None:
+            self._lib.shoot_lbfgs_destroy(self._opt)
+            self._opt = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lbfgs(pairs: Sequence[PairSpec], T: int, iters: int, m: int = 5, c1: float = 1e-4, trials: int = 8,
+          flags: int = 0):
+    """L-BFGS on every pair's p0 (updated in place). Returns the plan, the cost
+    history [iters, n_pairs] (cost at the start of each iteration) and the
+    gradient evaluations of each iteration."""
+    plan = Plan(pairs, T, flags, outputs=("grad", "cost"))
+    opt = LBFGS(plan, m, c1, trials)
+    hist, evals = [], []
+    for _ in range(iters):
+        c, e = opt.step()
+        hist.append(c)
+        evals.append(e)
+    opt.close()
+    return plan, hist, evals
+
+
 # ---------------------------------------------------------------- autograd
 
 _PLAN_CACHE: "OrderedDict[tuple, Plan]" = OrderedDict()

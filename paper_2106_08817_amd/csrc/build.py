@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["kernels.hip", "kernels_unfused.hip", "shoot_api.cpp"]
+SOURCES = ["kernels.hip", "kernels_unfused.hip", "kernels_opt.hip", "shoot_api.cpp", "lbfgs_api.cpp"]
 OUT = os.path.join(PKG, "libshoot.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "plan_access.h"
 #include "unfused.h"
 
 using namespace shoot;
@@ -556,6 +557,15 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
 }
 
 }  // namespace
+
+void shoot_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
+
+int shoot_internal_pairs(shoot_plan p, const shoot_pair** pairs, int* bound) {
+  if (!p) return -1;
+  if (pairs) *pairs = p->pairs.data();
+  if (bound) *bound = (p->ws != nullptr || p->uf != nullptr) ? 1 : 0;
+  return p->npairs;
+}
 
 // ====================================================================== C ABI
 // The library is built with hidden visibility; only this block is exported.

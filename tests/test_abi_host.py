@@ -159,3 +159,28 @@ def test_descend_requires_bind_and_validates_step():
     st, h = create([pair(shape=(40, 52))], T=4, flags=_lib.SHOOT_UNFUSED)
     assert lib.shoot_descend(h, 1.0, 1, None) == _lib.SHOOT_E_ARG
     lib.shoot_plan_destroy(h)
+
+
+def test_lbfgs_validation_host_side():
+    lib = _lib.load()
+    st, h = create([pair(shape=(40, 52))], T=4)
+    assert st == _lib.SHOOT_OK
+    o = ctypes.c_void_p()
+    assert lib.shoot_lbfgs_create(h, 0, 1e-4, 8, ctypes.byref(o)) == _lib.SHOOT_E_ARG      # m
+    assert lib.shoot_lbfgs_create(h, 5, 1.5, 8, ctypes.byref(o)) == _lib.SHOOT_E_ARG       # c1
+    assert lib.shoot_lbfgs_create(h, 5, 1e-4, 0, ctypes.byref(o)) == _lib.SHOOT_E_ARG      # trials
+    assert lib.shoot_lbfgs_create(None, 5, 1e-4, 8, ctypes.byref(o)) == _lib.SHOOT_E_ARG
+    assert lib.shoot_lbfgs_create(h, 5, 1e-4, 8, ctypes.byref(o)) == _lib.SHOOT_OK
+    n = ctypes.c_size_t()
+    assert lib.shoot_lbfgs_workspace_bytes(o, ctypes.byref(n)) == _lib.SHOOT_OK and n.value > 0
+    assert lib.shoot_lbfgs_step(o, None) == _lib.SHOOT_E_STATE                             # not bound
+    assert lib.shoot_lbfgs_bind(o, FAKE + 4, n.value, None) == _lib.SHOOT_E_WORKSPACE
+    assert lib.shoot_lbfgs_bind(o, FAKE, n.value - 1, None) == _lib.SHOOT_E_WORKSPACE
+    assert lib.shoot_lbfgs_destroy(o) == _lib.SHOOT_OK
+    lib.shoot_plan_destroy(h)
+    p = pair(shape=(40, 52))
+    p.out_grad = None
+    st, h = create([p], T=4)
+    assert lib.shoot_lbfgs_create(h, 5, 1e-4, 8, ctypes.byref(o)) == _lib.SHOOT_E_ARG      # needs out_grad
+    assert b"out_grad" in lib.shoot_last_error()
+    lib.shoot_plan_destroy(h)
