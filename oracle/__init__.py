@@ -23,6 +23,11 @@ Parity status of each function (what pins it; tests/test_oracle_*.py):
 * deformation: identity at zero momentum, the clamped foot in closed form at
   T = 1, a component that stays the identity when nothing moves along its
   axis, values within the grid.
+* step_eulerian_given_v, step_mixed_given_v, shoot(scheme=...): identity at
+  zero momentum, exact transport of affine fields by a constant velocity in
+  the interior, first-order convergence of the Eulerian time stepping, and
+  the stability behaviour the paper reports (Eulerian ripples and failure
+  where the semi-Lagrangian scheme keeps the image in range).
 * energy: diagnostic only, parity unpinned (the paper gives no numbers).
 * gradient_descent: parity unpinned (driver; its steps are pinned above).
 * lbfgs (oracle/lbfgs.py): two-loop recursion against the explicit BFGS
@@ -53,7 +58,9 @@ from .shooting import (  # noqa: F401
     smooth,
     step,
     step_adjoint,
+    step_eulerian_given_v,
     step_given_v,
+    step_mixed_given_v,
     velocity,
 )
 from .lbfgs import lbfgs, minimize as lbfgs_minimize, two_loop  # noqa: F401,E402

@@ -239,6 +239,33 @@ def step(I, z, rho: float, dt: float, w: np.ndarray):
     return I1, z1, aux
 
 
+def step_eulerian_given_v(I, z, v, rho: float, dt: float):
+    """One step of the Eulerian scheme the paper compares against (option 1 of
+    the semi-Lagrangian section; Eq. 5 and the continuity equation integrated
+    at fixed grid points): explicit Euler in time with the same clamped central
+    differences D as the rest of the scheme,
+    I' = I - dt sum_a v_a D_a I + rho dt z,   z' = z - dt sum_a D_a (z v_a).
+    Readings: the paper names the scheme but not its discretisation."""
+    I = _as64(I)
+    z = _as64(z)
+    d = I.ndim
+    adv = sum(_as64(v[a]) * diff(I, a) for a in range(d))
+    flux = sum(diff(z * _as64(v[a]), a) for a in range(d))
+    return I - dt * adv + rho * dt * z, z - dt * flux
+
+
+def step_mixed_given_v(I, z, v, rho: float, dt: float):
+    """Option 3 of the semi-Lagrangian section: the image is moved
+    semi-Lagrangianly (as in step_given_v) and the momentum by the Eulerian
+    continuity update of step_eulerian_given_v."""
+    I1, _, _ = step_given_v(I, z, v, rho, dt)
+    _, z1 = step_eulerian_given_v(I, z, v, rho, dt)
+    return I1, z1
+
+
+SCHEMES = ("sl", "eulerian", "mixed")
+
+
 @dataclass
 class Trajectory:
     I: List[np.ndarray]          # I_0 .. I_T
@@ -246,18 +273,28 @@ class Trajectory:
     v: List[List[np.ndarray]]    # v_0 .. v_{T-1}
 
 
-def shoot(S, p0, rho: float, sigma: float, T: int) -> Trajectory:
+def shoot(S, p0, rho: float, sigma: float, T: int, scheme: str = "sl") -> Trajectory:
     """Geodesic shooting from (I_0, z_0) = (S, p0) over T steps of dt = 1/T
-    (Methods, Eq. 3 integrated with the full semi-Lagrangian scheme)."""
+    (Methods, Eq. 3 integrated with the full semi-Lagrangian scheme; scheme
+    "eulerian" or "mixed" integrates with the alternatives the paper compares,
+    step_eulerian_given_v and step_mixed_given_v, from the same velocity)."""
     if T < 1:
         raise ValueError("T must be >= 1")
+    if scheme not in SCHEMES:
+        raise ValueError(f"scheme must be one of {SCHEMES}")
     w = gaussian_taps(sigma)
     dt = 1.0 / T
     I, z = _as64(S).copy(), _as64(p0).copy()
     Is, zs, vs = [I], [z], []
     for _ in range(T):
-        I, z, aux = step(I, z, F64(rho), dt, w)
-        vs.append(aux["v"])
+        if scheme == "sl":
+            I, z, aux = step(I, z, F64(rho), dt, w)
+            v = aux["v"]
+        else:
+            v = velocity(I, z, w)
+            fn = step_eulerian_given_v if scheme == "eulerian" else step_mixed_given_v
+            I, z = fn(I, z, v, F64(rho), dt)
+        vs.append(v)
         Is.append(I)
         zs.append(z)
     return Trajectory(Is, zs, vs)

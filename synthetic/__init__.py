@@ -20,6 +20,7 @@ from .phantoms import (  # noqa: F401
     make_p0,
     disk_pair,
     phantom_pair,
+    ripple_case,
     workload,
     small_pair,
 )

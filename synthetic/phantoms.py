@@ -222,6 +222,23 @@ def disk_pair(seed: int = 1, p0_kind: str = "random", size: int = 64) -> Pair:
                 sigma=float(np.float32(3.0)), meta={"seed": seed, "p0": p0_kind})
 
 
+def ripple_case(size: int = 64, amplitude: float = 100.0):
+    """Stand-in for the paper's scheme comparison (Results, Fig. 1: a shot from
+    an LDDMM momentum toward a 'C' picture): a sharp disk (radius 0.3 size,
+    1-px blur) as source, the disk with a notch cut on its right side as the
+    'C' target, and an initial momentum concentrated on the part of the disk
+    edge that must move, amplitude * (S - J) (rho = 0 is intended)."""
+    yy, xx = _grid((size, size))
+    c = (size - 1) / 2.0
+    r = 0.3 * size
+    disk = ((yy - c) ** 2 + (xx - c) ** 2 <= r ** 2).astype(np.float64)
+    notch = ((np.abs(yy - c) <= 0.12 * size) & (xx >= c)).astype(np.float64)
+    S = ndimage.gaussian_filter(disk, 1.0, mode="constant")
+    J = ndimage.gaussian_filter(disk * (1.0 - notch), 1.0, mode="constant")
+    p0 = amplitude * (S - J)
+    return _f32(S), _f32(J), _f32(p0)
+
+
 def phantom_pair(shape: Sequence[int], seed: int, rho: float, sigma: float,
                  p0_kind: str = "realistic", warp_sigma: Optional[float] = None,
                  max_disp: Optional[float] = None) -> Pair:
