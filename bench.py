@@ -242,6 +242,49 @@ def copy_rate(nbytes: int, torch, reps: int = 20) -> float:
     return 8.0 * n * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
 
 
+def scheme_comparison(wl, steps, warmup, torch, api, synthetic):
+    """The integration options the paper compares: shoot_forward time over the
+    workload for each, and the stability rerun (rho = 0 shot of a disk toward a
+    'C': range overshoot of I_T and total variation of z_T; the Eulerian
+    scheme at dt = 1/38, the semi-Lagrangian ones at 1/20)."""
+    def specs_of(pairs):
+        return [api.PairSpec(torch.from_numpy(p.source).cuda(), torch.from_numpy(p.p0).cuda(), p.rho, p.sigma,
+                             p.lam, torch.from_numpy(p.target).cuda()) for p in pairs]
+
+    out = {}
+    flags = {"semi_lagrangian": 0, "eulerian": api.SHOOT_SCHEME_EULERIAN, "mixed": api.SHOOT_SCHEME_MIXED}
+    for name, f in flags.items():
+        plan = api.Plan(specs_of(wl.pairs), wl.T, f, outputs=("image", "momentum", "cost"))
+        for _ in range(warmup):
+            plan.forward()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.forward()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = {"forward_ms": e0.elapsed_time(e1) / steps}
+        plan.close()
+    S, J, p0 = synthetic.ripple_case()
+    lo, hi = float(S.min()), float(S.max())
+    for name, f, T in (("semi_lagrangian", 0, 20), ("eulerian", api.SHOOT_SCHEME_EULERIAN, 38),
+                       ("mixed", api.SHOOT_SCHEME_MIXED, 20)):
+        t = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+        plan = api.Plan([api.PairSpec(t(S), t(p0), 0.0, 3.0, 0.01, t(J))], T, f, outputs=("image", "momentum"))
+        plan.forward()
+        torch.cuda.synchronize()
+        I = plan.out_image[0].double()
+        z = plan.out_momentum[0].double()
+        over = max(float(I.max()) - hi, lo - float(I.min()), 0.0)
+        tv = float(sum(z.diff(dim=a).abs().sum() for a in range(z.dim())))
+        out[name].update({"ripple_case_T": T, "ripple_case_overshoot": over, "ripple_case_z_total_variation": tv})
+        plan.close()
+    return out
+
+
 def lbfgs_rate(wl, iters, torch, api):
     """Wall time of batched L-BFGS iterations over the workload (every pair at
     once; each iteration evaluates cost + gradient once per line-search trial
@@ -459,6 +502,7 @@ def main():
             p2.close()
         extra["forward_deformation"] = forward_deformation(wl, args.steps, args.warmup, torch, api)
         extra["lbfgs"] = lbfgs_rate(wl, 4, torch, api)
+        extra["schemes"] = scheme_comparison(wl, args.steps, args.warmup, torch, api, synthetic)
         if args.workload != "c5" and not args.no_3d:
             r5 = measure("c5", args.steps_3d, 2, 1, args.flags, not args.no_autotune, torch, api, synthetic)
             for key in ("secs", "step_bytes"):

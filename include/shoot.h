@@ -113,6 +113,13 @@ typedef struct shoot_plan_s* shoot_plan;
 #define SHOOT_UNFUSED 2u               /* per-pair, one kernel per primitive (baseline) */
 #define SHOOT_NO_GRAPH 4u              /* launch kernels eagerly, no internal HIP graph */
 #define SHOOT_FORCE_GLOBAL_SCATTER 8u  /* adjoint scatter through global atomics only */
+/* Integration options the paper compares with the full semi-Lagrangian scheme
+ * (semi-Lagrangian section; forward and cost only, SHOOT_E_ARG for the
+ * gradient): Eulerian: explicit Euler with clamped central differences,
+ * I' = I - dt sum_a v_a D_a I + rho dt z, z' = z - dt sum_a D_a (z v_a);
+ * mixed: semi-Lagrangian image, Eulerian momentum. */
+#define SHOOT_SCHEME_EULERIAN 16u
+#define SHOOT_SCHEME_MIXED 32u
 
 /* Library version string. Never NULL. */
 const char* shoot_version(void);

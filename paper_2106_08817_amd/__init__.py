@@ -5,6 +5,8 @@ from .api import (  # noqa: F401
     SHOOT_FORCE_GLOBAL_SCATTER,
     SHOOT_FULL_STORE,
     SHOOT_NO_GRAPH,
+    SHOOT_SCHEME_EULERIAN,
+    SHOOT_SCHEME_MIXED,
     SHOOT_UNFUSED,
     LBFGS,
     PairSpec,

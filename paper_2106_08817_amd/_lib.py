@@ -33,6 +33,8 @@ SHOOT_FULL_STORE = 1
 SHOOT_UNFUSED = 2
 SHOOT_NO_GRAPH = 4
 SHOOT_FORCE_GLOBAL_SCATTER = 8
+SHOOT_SCHEME_EULERIAN = 16
+SHOOT_SCHEME_MIXED = 32
 SHOOT_TUNE_COUNT = 5
 
 # Every function the header declares, with its ctypes signature.

@@ -20,7 +20,7 @@ import torch
 
 from . import _lib
 from ._lib import (SHOOT_FORCE_GLOBAL_SCATTER, SHOOT_FULL_STORE, SHOOT_NO_GRAPH,  # noqa: F401
-                   SHOOT_UNFUSED, ShootError)
+                   SHOOT_SCHEME_EULERIAN, SHOOT_SCHEME_MIXED, SHOOT_UNFUSED, ShootError)
 
 __all__ = ["PairSpec", "Plan", "ShootCost", "shoot_cost", "gradient_descent",
            "SHOOT_FULL_STORE", "SHOOT_UNFUSED", "SHOOT_NO_GRAPH", "SHOOT_FORCE_GLOBAL_SCATTER"]

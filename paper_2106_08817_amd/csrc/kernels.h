@@ -18,6 +18,7 @@ struct AdvectArgs {
   float* red_reg;       // first step: per-tile regulariser partials, or null
   float* red_ssd;       // last step: per-tile data-term partials, or null
   int last;             // 1 at t = T - 1 (write the outputs)
+  int scheme;           // 0 semi-Lagrangian, 1 Eulerian, 2 semi-Lagrangian image + Eulerian momentum
 };
 
 struct AdjArgs {

@@ -339,7 +339,11 @@ __device__ __forceinline__ float mlerp(const float* c, const float f[3]) {
   return fmaf(f[0], b, (1.f - f[0]) * a);
 }
 
-template <int NDIM, int GS>
+// SCHEME 0: the semi-Lagrangian step. SCHEME 1: the Eulerian step (explicit
+// Euler, clamped central differences: I' = I - dt sum_a v_a D_a I + rho dt z,
+// z' = z - dt sum_a D_a (z v_a)). SCHEME 2: semi-Lagrangian image, Eulerian
+// momentum.
+template <int NDIM, int GS, int SCHEME = 0>
 __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                                const float* __restrict__ Vg, const float* __restrict__ stg,
                                                float* __restrict__ stog, AdvectArgs A) {
@@ -396,8 +400,8 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const unsigned gi = c0 + (unsigned)(j >> 2) * sxy + (unsigned)(((j >> 1) & 1) * nx + (j & 1));
-        iv[g][j] = gld(I, gi);
-        zv[g][j] = gld(Z, gi);
+        iv[g][j] = SCHEME == 1 ? 0.f : gld(I, gi);
+        zv[g][j] = SCHEME == 1 ? 0.f : gld(Z, gi);
       }
     }
     float In[GS], zn[GS];
@@ -407,6 +411,28 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
       const float zh = mlerp<NDIM>(zv[g], fr[g]);
       In[g] = fmaf(rdt, zh, Ih);
       zn[g] = zh * fmaf(-dt, div_of<NDIM>(vn[g]), 1.f);
+    }
+    if (SCHEME != 0) {
+      // Eulerian momentum (and image for SCHEME 1) at q, axes in array order
+#pragma unroll
+      for (int g = 0; g < GS; ++g) {
+        const unsigned i0 = idx[g];
+        const int q3[3] = {qz[g], qy[g], qx[g]};
+        const int n3[3] = {nz, ny, nx};
+        const unsigned s3[3] = {sxy, (unsigned)nx, 1u};
+        const float Iq = gld(I, i0), zq = gld(Z, i0);
+        float adv = 0.f, flux = 0.f;
+#pragma unroll
+        for (int c = 0; c < NDIM; ++c) {
+          const int a = 3 - NDIM + c;                 // array axis of channel c
+          const int vi = 2 * (2 - a);                 // vn holds (+, -) per axis, x first
+          const unsigned sp = (unsigned)up(q3[a], n3[a], (int)s3[a]), sm = (unsigned)dn(q3[a], (int)s3[a]);
+          adv = fmaf(v[g][c], 0.5f * (gld(I, i0 + sp) - gld(I, i0 - sm)), adv);
+          flux = fmaf(0.5f, gld(Z, i0 + sp) * vn[g][vi] - gld(Z, i0 - sm) * vn[g][vi + 1], flux);
+        }
+        if (SCHEME == 1) In[g] = fmaf(rdt, zq, fmaf(-dt, adv, Iq));
+        zn[g] = fmaf(-dt, flux, zq);
+      }
     }
 #pragma unroll
     for (int g = 0; g < GS; ++g) {
@@ -1460,6 +1486,16 @@ hipError_t launch_spass(int ndim, bool passz, int mode, int rb, const PairDev* p
 }
 
 hipError_t launch_advect(int ndim, int opt, int nt, const AdvectArgs& a, hipStream_t s) {
+  if (a.scheme == 1 || a.scheme == 2) {
+    if (ndim == 2) {
+      if (a.scheme == 1) k_advect<2, ADV_BATCH[0], 1><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+      else k_advect<2, ADV_BATCH[0], 2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    } else {
+      if (a.scheme == 1) k_advect<3, ADV_BATCH[1], 1><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+      else k_advect<3, ADV_BATCH[1], 2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
+    }
+    return post();
+  }
   if (ndim == 2) {
     if (opt == 0) k_advect_lds<2><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);
     else k_advect<2, ADV_BATCH[0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.st_out, a);

@@ -403,6 +403,7 @@ hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
   a.last = (first_pass && t == T - 1) ? 1 : 0;
   a.red_reg = (first_pass && t == 0) ? c.rreg : nullptr;
   a.red_ssd = (first_pass && t == T - 1) ? c.rssd : nullptr;
+  a.scheme = (c.p->flags & SHOOT_SCHEME_EULERIAN) ? 1 : ((c.p->flags & SHOOT_SCHEME_MIXED) ? 2 : 0);
   if (a.last && is_grad(op)) { a.ab_out = AB(c, T); a.sc_zero = c.sc; }
   LAUNCH(KI_ADVECT, launch_advect(c.p->ndim, c.o_adv, c.ntb, a, c.s));
   return hipSuccess;
@@ -508,6 +509,8 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
     if (op != OP_FORWARD && !q.target) return fail(SHOOT_E_ARG, "target is NULL (pair " + std::to_string(i) + ")");
     if (op == OP_COST && !q.out_cost) return fail(SHOOT_E_ARG, "out_cost is NULL (pair " + std::to_string(i) + ")");
     if (is_grad(op) && !q.out_grad) return fail(SHOOT_E_ARG, "out_grad is NULL (pair " + std::to_string(i) + ")");
+    if (is_grad(op) && (p->flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED)))
+      return fail(SHOOT_E_ARG, "the gradient is available for the semi-Lagrangian scheme only");
     if (op >= OP_DESCEND && !q.out_cost) return fail(SHOOT_E_ARG, "out_cost is NULL (pair " + std::to_string(i) + ")");
   }
   int dev = -1;
@@ -580,8 +583,13 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
                                size_t budget_bytes, shoot_plan* out) {
   if (!out) return fail(SHOOT_E_ARG, "out is NULL");
   *out = nullptr;
-  const uint32_t known = SHOOT_FULL_STORE | SHOOT_UNFUSED | SHOOT_NO_GRAPH | SHOOT_FORCE_GLOBAL_SCATTER;
+  const uint32_t known = SHOOT_FULL_STORE | SHOOT_UNFUSED | SHOOT_NO_GRAPH | SHOOT_FORCE_GLOBAL_SCATTER |
+                         SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED;
   if (flags & ~known) return fail(SHOOT_E_ARG, "unknown flag bits");
+  const uint32_t schemes = flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED);
+  if (schemes == (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED))
+    return fail(SHOOT_E_ARG, "SHOOT_SCHEME_EULERIAN and SHOOT_SCHEME_MIXED exclude each other");
+  if (schemes && (flags & SHOOT_UNFUSED)) return fail(SHOOT_E_ARG, "the unfused path integrates semi-Lagrangianly only");
   shoot_status st = validate(pairs, n_pairs, T);
   if (st != SHOOT_OK) return st;
   shoot_plan_s* p = new (std::nothrow) shoot_plan_s();
@@ -712,6 +720,7 @@ shoot_status shoot_autotune(shoot_plan p, void* stream) {
   int op = OP_GRAD;
   for (const shoot_pair& q : p->pairs)
     if (!q.target || !q.out_grad) op = OP_FORWARD;
+  if (p->flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED)) op = OP_FORWARD;
   // kernel families timed for each choice
   static const int fam[TUNE_N][3] = {
       {KI_XPASS_M, KI_XPASS_V, -1},

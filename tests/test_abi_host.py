@@ -184,3 +184,16 @@ def test_lbfgs_validation_host_side():
     assert lib.shoot_lbfgs_create(h, 5, 1e-4, 8, ctypes.byref(o)) == _lib.SHOOT_E_ARG      # needs out_grad
     assert b"out_grad" in lib.shoot_last_error()
     lib.shoot_plan_destroy(h)
+
+
+def test_scheme_flags_validation():
+    lib = _lib.load()
+    E, M = _lib.SHOOT_SCHEME_EULERIAN, _lib.SHOOT_SCHEME_MIXED
+    st, h = create([pair()], flags=E | M)
+    assert st == _lib.SHOOT_E_ARG
+    st, h = create([pair()], flags=E | _lib.SHOOT_UNFUSED)
+    assert st == _lib.SHOOT_E_ARG
+    for f in (E, M):
+        st, h = create([pair()], flags=f)
+        assert st == _lib.SHOOT_OK
+        lib.shoot_plan_destroy(h)
