@@ -85,7 +85,8 @@ typedef enum shoot_status {
  *                     weights, so that S o psi_T ~ I_T for rho = 0 (the
  *                     deformation grids of the Results section; the flow of
  *                     Methods integrated semi-Lagrangianly). Component a is
- *                     the grid coordinate along array axis a.
+ *                     the grid coordinate along array axis a. Not available
+ *                     with SHOOT_UNFUSED (SHOOT_E_ARG at plan creation).
  * rho >= 0 weighs the intensity residual; sigma > 0 is the kernel width in
  * pixels (sigma < 32/3, i.e. radius floor(3 sigma) <= 31); lambda >= 0 weighs
  * the regulariser.

@@ -590,6 +590,10 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
   if (schemes == (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED))
     return fail(SHOOT_E_ARG, "SHOOT_SCHEME_EULERIAN and SHOOT_SCHEME_MIXED exclude each other");
   if (schemes && (flags & SHOOT_UNFUSED)) return fail(SHOOT_E_ARG, "the unfused path integrates semi-Lagrangianly only");
+  if (flags & SHOOT_UNFUSED)
+    for (int i = 0; i < n_pairs && pairs; ++i)
+      if (pairs[i].out_deformation)
+        return fail(SHOOT_E_ARG, "the unfused path has no deformation output (pair " + std::to_string(i) + ")");
   shoot_status st = validate(pairs, n_pairs, T);
   if (st != SHOOT_OK) return st;
   shoot_plan_s* p = new (std::nothrow) shoot_plan_s();

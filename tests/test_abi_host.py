@@ -197,3 +197,13 @@ def test_scheme_flags_validation():
         st, h = create([pair()], flags=f)
         assert st == _lib.SHOOT_OK
         lib.shoot_plan_destroy(h)
+
+
+def test_unfused_plan_rejects_deformation_output():
+    p = pair()
+    p.out_deformation = FAKE + 20480
+    st, h = create([p], flags=_lib.SHOOT_UNFUSED)
+    assert st == _lib.SHOOT_E_ARG
+    st, h = create([p])
+    assert st == _lib.SHOOT_OK
+    _lib.load().shoot_plan_destroy(h)
