@@ -156,7 +156,8 @@ shoot_status shoot_plan_bind(shoot_plan plan, void* workspace, size_t bytes, voi
 /*
  * Launch-shape tuning. A plan carries SHOOT_TUNE_COUNT choices, each 0 or 1
  * (0 = default), in this order:
- *   [0] x-pass rows per tile (one full fill batch / half of it)
+ *   [0] x-pass rows per tile (at most one output group per thread / one
+ *       full fill batch)
  *   [1] strided (y/z) pass outputs per thread (16 / 8)
  *   [2] advection: from an LDS-staged tile / by global gathers
  *   [3] adjoint load batch (voxels per thread whose loads are in flight

@@ -258,16 +258,19 @@ void build_wave(shoot_plan_s* p, Wave& w) {
           for (int x0 = 0; x0 < P.nx; x0 += BX) w.tb.push_back(Tile{pi, x0, y0, z0});
     }
     P.elem_count = (int)w.tb.size() - P.elem_first;
-    // x-pass tiles: rows of the pair. Option 0: as many rows as one batch of
-    // the fill covers (XSEG 64-column segments per wave); option 1: half of
-    // that. Both within the LDS budget.
+    // x-pass tiles: rows of the pair, at most as many as one batch of the fill
+    // covers (XSEG 64-column segments per wave). Option 0: also at most one
+    // group of four outputs per thread (nr * G4 <= NT), so the tap loop runs
+    // in a single round; option 1: the full fill batch. Both within the LDS
+    // budget.
     const size_t rb = xpass_row_bytes(p->ndim, P.nx, P.ntap4);
-    const int L = 4 * ((P.nx + 3) / 4 + P.ntap4);
+    const int G4 = (P.nx + 3) / 4;
+    const int L = 4 * (G4 + P.ntap4);
     const int nch = (L + 63) / 64;
     const int rows = P.nz * P.ny;
     for (int opt = 0; opt < 2; ++opt) {
       int nr = std::max(1, XSEG * (NT / 64) / nch);
-      if (opt == 1) nr = std::max(1, nr / 2);
+      if (opt == 0) nr = std::max(1, std::min(nr, NT / G4));
       nr = std::min(nr, std::max(1, (int)(XPASS_LDS_CAP / rb)));
       if (opt == 0) P.xrows = nr;
       for (int r0 = 0; r0 < rows; r0 += nr) {

@@ -36,10 +36,10 @@ constexpr int ADJ_BATCH[2][2] = {{2, 4}, {1, 2}};
 constexpr int ADJ_RING_BATCH2 = 2, ADJ_RING_BATCH3 = 1;
 constexpr int EPI_BATCH[2] = {4, 2};  // [ndim - 2], epilogue without staging
 // Tuning choices of a plan (each 0 or 1; 0 is the default): x-pass rows per
-// tile (full fill batch / half), strided-pass outputs per thread
-// (SPASS_RB), advection from an LDS-staged tile or by global gathers, the
-// adjoint's load batch, and the epilogue from an LDS-staged tile or direct
-// loads.
+// tile (one output group per thread / the full fill batch), strided-pass
+// outputs per thread (SPASS_RB), advection from an LDS-staged tile or by
+// global gathers, the adjoint's load batch, and the epilogue from an
+// LDS-staged tile or direct loads.
 enum TuneKnob { TUNE_XPASS = 0, TUNE_SPASS, TUNE_ADVECT, TUNE_ADJ, TUNE_EPI, TUNE_N };
 // arrival points staged per adjoint tile: the tile grown by the bound on each side
 template <int NDIM>
