@@ -368,7 +368,13 @@ int st_slot(const shoot_plan_s* p, int t) {
   if (fullstore(p)) return t;
   return (t % p->k == 0) ? t / p->k : p->nck + (t % p->k) - 1;
 }
-int v_slot(const shoot_plan_s* p, int t) { return fullstore(p) ? t : t % p->k; }
+// Velocity slots: with checkpoints, k - 1 slots for the steps inside a
+// segment, then one per checkpoint (a checkpoint keeps its state and its
+// velocity, so a recomputed segment starts with the advection).
+int v_slot(const shoot_plan_s* p, int t) {
+  if (fullstore(p)) return t;
+  return (t % p->k == 0) ? p->k - 1 + t / p->k : (t % p->k) - 1;
+}
 float* ST(const Ctx& c, int t) { return c.st + (size_t)st_slot(c.p, t) * 2 * c.ntot; }
 float* VS(const Ctx& c, int t) { return c.vs + (size_t)v_slot(c.p, t) * c.p->ndim * c.ntot; }
 float* AB(const Ctx& c, int t) { return c.ab + (size_t)(t & 1) * 2 * c.ntot; }
@@ -393,10 +399,13 @@ hipError_t velocity(const Ctx& c, int t) {
   return hipSuccess;
 }
 
-// One forward step t -> t + 1. `store` writes state t + 1 to its slot.
-hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass) {
-  hipError_t e = velocity(c, t);
-  if (e != hipSuccess) return e;
+// One forward step t -> t + 1. `store` writes state t + 1 to its slot;
+// `have_v`: the velocity of step t is already in its slot.
+hipError_t fwd_step(const Ctx& c, int t, bool store, int op, bool first_pass, bool have_v = false) {
+  if (!have_v) {
+    hipError_t e = velocity(c, t);
+    if (e != hipSuccess) return e;
+  }
   const int T = c.p->T;
   AdvectArgs a{};
   a.pd = c.pd; a.tl = c.tb; a.V = VS(c, t); a.st = ST(c, t);
@@ -469,10 +478,12 @@ hipError_t run_grad(const Ctx& c) {
   for (int s = nseg - 1; s >= 0; --s) {
     const int t0 = s * k, t1 = std::min(T, t0 + k);
     if (s != nseg - 1) {
-      // restore states t0+1 .. t1-1 and velocities t0 .. t1-1 from checkpoint
-      // t0 (the last step needs only its velocity: state t1 is a checkpoint)
+      // restore states t0+1 .. t1-1 and velocities t0+1 .. t1-1 from
+      // checkpoint t0, whose velocity the forward pass kept (the last step
+      // needs only its velocity: state t1 is a checkpoint)
       for (int t = t0; t < t1; ++t) {
-        e = t + 1 < t1 ? fwd_step(c, t, true, OP_GRAD, false) : velocity(c, t);
+        if (t + 1 < t1) e = fwd_step(c, t, true, OP_GRAD, false, t == t0);
+        else e = t == t0 ? hipSuccess : velocity(c, t);
         if (e != hipSuccess) return e;
       }
     }
@@ -617,7 +628,7 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     p->nv = T;
   } else {
     p->nst = p->nck + p->k - 1;
-    p->nv = p->k;
+    p->nv = p->k - 1 + p->nck;
   }
   if (flags & SHOOT_UNFUSED) {
     p->uf = unfused::create(p->pairs.data(), n_pairs, T);
