@@ -121,6 +121,21 @@ typedef struct shoot_plan_s* shoot_plan;
  * mixed: semi-Lagrangian image, Eulerian momentum. */
 #define SHOOT_SCHEME_EULERIAN 16u
 #define SHOOT_SCHEME_MIXED 32u
+/* Concurrent lanes: the pairs of an admission wave are split into up to n
+ * lanes of balanced voxel count (each keeping the pairs' order); every lane
+ * runs the whole schedule on its own stream, forked from and joined back into
+ * the caller's stream, so that the kernels of different lanes overlap (a
+ * lane's pairs fill the GPU while another lane's launch drains). Results are
+ * identical whatever the lane count: pairs are independent and every pair's
+ * arithmetic is the same. SHOOT_LANES(n), 1 <= n <= SHOOT_MAX_LANES, fixes the
+ * count; without it a plan takes 3 lanes in 2-D and 2 in 3-D (at most one
+ * lane per pair). A plan of n lanes uses n streams (the caller's and n - 1
+ * of its own); lanes gain only while the device has a hardware queue for
+ * each. Inside the caller's stream capture the lanes run one after another
+ * on the caller's stream. */
+#define SHOOT_MAX_LANES 8
+#define SHOOT_LANES(n) ((((uint32_t)(n)) & 15u) << 8)
+#define SHOOT_LANES_MASK (15u << 8)
 
 /* Library version string. Never NULL. */
 const char* shoot_version(void);
@@ -133,8 +148,8 @@ const char* shoot_last_error(void);
  * (dt = 1/T). All pairs must have the same ndim. The descriptors are copied;
  * their device pointers are used from shoot_plan_bind on. Host-only: no HIP
  * call is made. budget_bytes caps the workspace (0 = no cap): pairs are
- * grouped into waves that each fit, run one after another in the same
- * workspace; SHOOT_E_BUDGET if a single pair does not fit.
+ * grouped into waves that each fit (with their lanes), run one after another
+ * in the same workspace; SHOOT_E_BUDGET if a single pair does not fit.
  * On success *out receives the plan; on failure *out is set to NULL.
  */
 shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t T,
@@ -145,6 +160,10 @@ shoot_status shoot_plan_workspace_bytes(shoot_plan plan, size_t* bytes);
 
 /* Number of admission waves the plan runs (1 unless a budget forced more). */
 shoot_status shoot_plan_waves(shoot_plan plan, int32_t* waves);
+
+/* Largest number of concurrent lanes of an admission wave (1 for
+ * SHOOT_UNFUSED plans). */
+shoot_status shoot_plan_lanes(shoot_plan plan, int32_t* lanes);
 
 /*
  * Attach the caller-owned device workspace and upload the plan's descriptors
@@ -255,9 +274,11 @@ shoot_status shoot_lbfgs_destroy(shoot_lbfgs opt);
 
 /*
  * Diagnostics. With profiling enabled, execution calls run eagerly (no graph)
- * with a HIP event pair around every kernel launch on the launch stream, and
- * synchronise the stream before returning; per-kernel launch counts and total
- * milliseconds accumulate until reset. shoot_plan_kernel_stats returns
+ * and synchronise the stream before returning. The lanes of a wave run one
+ * after another on the caller's stream, the k-th launches of all lanes
+ * together between one HIP event pair, so one timed launch covers all the
+ * pairs of the wave. Per-kernel launch counts and total milliseconds
+ * accumulate until reset. shoot_plan_kernel_stats returns
  * SHOOT_E_ARG for an index past the last kernel; *name stays owned by the
  * library.
  */

@@ -4,6 +4,7 @@ hand-written discrete adjoint (dH/dp0) behind a C ABI (include/shoot.h)."""
 from .api import (  # noqa: F401
     SHOOT_FORCE_GLOBAL_SCATTER,
     SHOOT_FULL_STORE,
+    SHOOT_LANES,
     SHOOT_NO_GRAPH,
     SHOOT_SCHEME_EULERIAN,
     SHOOT_SCHEME_MIXED,

@@ -35,6 +35,14 @@ SHOOT_NO_GRAPH = 4
 SHOOT_FORCE_GLOBAL_SCATTER = 8
 SHOOT_SCHEME_EULERIAN = 16
 SHOOT_SCHEME_MIXED = 32
+SHOOT_MAX_LANES = 8
+SHOOT_LANES_MASK = 15 << 8
+
+
+def SHOOT_LANES(n: int) -> int:
+    """Plan flag fixing the number of concurrent lanes (1 <= n <= 8)."""
+    return (int(n) & 15) << 8
+
 SHOOT_TUNE_COUNT = 5
 
 # Every function the header declares, with its ctypes signature.
@@ -44,6 +52,7 @@ EXPORTS = {
     "shoot_plan_create": (c_int32, [c_void_p, c_int32, c_int32, c_uint32, c_size_t, POINTER(c_void_p)]),
     "shoot_plan_workspace_bytes": (c_int32, [c_void_p, POINTER(c_size_t)]),
     "shoot_plan_waves": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "shoot_plan_lanes": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_plan_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "shoot_autotune": (c_int32, [c_void_p, c_void_p]),
     "shoot_plan_get_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),

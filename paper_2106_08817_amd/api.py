@@ -19,11 +19,11 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (SHOOT_FORCE_GLOBAL_SCATTER, SHOOT_FULL_STORE, SHOOT_NO_GRAPH,  # noqa: F401
+from ._lib import (SHOOT_FORCE_GLOBAL_SCATTER, SHOOT_FULL_STORE, SHOOT_LANES, SHOOT_NO_GRAPH,  # noqa: F401
                    SHOOT_SCHEME_EULERIAN, SHOOT_SCHEME_MIXED, SHOOT_UNFUSED, ShootError)
 
 __all__ = ["PairSpec", "Plan", "ShootCost", "shoot_cost", "gradient_descent",
-           "SHOOT_FULL_STORE", "SHOOT_UNFUSED", "SHOOT_NO_GRAPH", "SHOOT_FORCE_GLOBAL_SCATTER"]
+           "SHOOT_FULL_STORE", "SHOOT_UNFUSED", "SHOOT_NO_GRAPH", "SHOOT_FORCE_GLOBAL_SCATTER", "SHOOT_LANES"]
 
 
 @dataclass
@@ -139,6 +139,13 @@ class Plan:
         w = ctypes.c_int32()
         _lib.check(self._lib.shoot_plan_waves(self._plan, ctypes.byref(w)), "shoot_plan_waves")
         return int(w.value)
+
+    @property
+    def lanes(self) -> int:
+        """Largest number of concurrent lanes of an admission wave."""
+        n = ctypes.c_int32()
+        _lib.check(self._lib.shoot_plan_lanes(self._plan, ctypes.byref(n)), "shoot_plan_lanes")
+        return int(n.value)
 
     def _call(self, fn, name, stream):
         if self._plan is None:

@@ -230,7 +230,8 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const unsigned ss = (unsigned)(PASSZ ? ny * nx : nx);
   const unsigned so = (unsigned)(PASSZ ? nx : ny * nx);
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  // wave-uniform, so the row of every fill load and its range test are scalar
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = t.a + lane;
   const bool xin = x < nx;
   const int s0 = t.c;
@@ -239,19 +240,20 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const unsigned base = (unsigned)t.b * so + (unsigned)min(x, nx - 1);
   const float* __restrict__ Fc = src + NDIM * P.off + c * N;
 
-  // fill: clamped loads, SFILL rows per thread in flight
+  // fill: clamped loads, SFILL rows per thread in flight; rows outside the
+  // axis and lanes beyond nx are zeroed when stored
   for (int j0 = wv; j0 < rows; j0 += SFILL * (NT / 64)) {
     float v[SFILL];
 #pragma unroll
     for (int u = 0; u < SFILL; ++u) {
       const int s = s0 - r + j0 + u * (NT / 64);
-      const float f = gld(Fc, base + (unsigned)clampi(s, 0, ns - 1) * ss);
-      v[u] = (xin && s >= 0 && s < ns) ? f : 0.f;
+      v[u] = gld(Fc, base + (unsigned)clampi(s, 0, ns - 1) * ss);
     }
 #pragma unroll
     for (int u = 0; u < SFILL; ++u) {
       const int j = j0 + u * (NT / 64);
-      if (j < rows) lds[j * 64 + lane] = v[u];
+      const int s = s0 - r + j;
+      if (j < rows) lds[j * 64 + lane] = (xin && s >= 0 && s < ns) ? v[u] : 0.f;
     }
   }
   __syncthreads();

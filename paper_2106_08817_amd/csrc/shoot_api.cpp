@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -57,6 +58,7 @@ struct Wave {
   size_t o_dmax = 0, o_rreg = 0, o_rssd = 0, o_eta = 0, o_prev = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
+  size_t field_off = 0;  // of this lane's fields inside the field region
 };
 
 struct Fields {  // byte offsets of the field arrays inside the field region
@@ -107,24 +109,6 @@ struct Prof {
   }
 };
 
-struct ProfScope {
-  Prof* p;
-  hipStream_t s;
-  Prof::Rec r;
-  ProfScope(Prof* p_, hipStream_t s_, int kid) : p(p_), s(s_) {
-    if (!p) return;
-    r.kid = kid;
-    r.a = p->get();
-    r.b = p->get();
-    if (r.a) (void)hipEventRecord(r.a, s);
-  }
-  ~ProfScope() {
-    if (!p) return;
-    if (r.b) (void)hipEventRecord(r.b, s);
-    p->pending.push_back(r);
-  }
-};
-
 }  // namespace
 
 struct shoot_plan_s {
@@ -132,13 +116,21 @@ struct shoot_plan_s {
   uint32_t flags = 0;
   size_t budget = 0;
   std::vector<shoot_pair> pairs;
+  // Waves (lanes) in execution order; groups[g] = (first wave, lane count):
+  // the lanes of a group run concurrently, groups one after another.
   std::vector<Wave> waves;
+  std::vector<std::pair<int, int>> groups;
+  int lanes = 1;                      // most lanes of a group
   size_t header_total = 0, field_max = 0, ws_bytes = 0;
   std::vector<unsigned char> blob;  // header image uploaded at bind
   char* ws = nullptr;
   int device = -1;
   hipStream_t cap = nullptr;
-  hipGraphExec_t graph[OP_N] = {};
+  std::vector<hipStream_t> side;      // streams of lanes 2 .. lanes-1 (lane 0 runs on the caller's
+                                      // stream, lane 1 on cap, idle outside graph capture)
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  std::vector<hipGraphExec_t> graph[OP_N];  // per wave
   float eta0 = 1.f;           // step of the descent after a reset
   bool descend_ready = false; // the descent's per-pair step state is initialised
   unfused::Plan* uf = nullptr;      // SHOOT_UNFUSED state
@@ -300,6 +292,31 @@ void build_wave(shoot_plan_s* p, Wave& w) {
   w.field_bytes = field_layout(p, w.ntot).end;
 }
 
+// Splits the pairs `ids` into at most L lanes of balanced voxel count (each
+// keeping the pairs' order) and builds them with consecutive field regions;
+// returns the bytes of the group's field region.
+size_t build_group(shoot_plan_s* p, const std::vector<int>& ids, int L, std::vector<Wave>& out) {
+  const int n = std::max(1, std::min(L, (int)ids.size()));
+  std::vector<int> order = ids;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return pair_voxels(p->pairs[a]) > pair_voxels(p->pairs[b]); });
+  std::vector<long long> load(n, 0);
+  out.assign(n, Wave());
+  for (int i : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    out[l].ids.push_back(i);
+    load[l] += pair_voxels(p->pairs[i]);
+  }
+  size_t off = 0;
+  for (Wave& w : out) {
+    std::sort(w.ids.begin(), w.ids.end());
+    build_wave(p, w);
+    w.field_off = off;
+    off += align_up(w.field_bytes, ALIGN);
+  }
+  return off;
+}
+
 size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   size_t o = base;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, ALIGN); return r; };
@@ -321,6 +338,12 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
 
 // -------------------------------------------------------------------- schedule
 
+// One recorded kernel launch of a wave's schedule.
+struct Launch {
+  int kid;
+  std::function<hipError_t()> fn;
+};
+
 struct Ctx {
   shoot_plan_s* p;
   Wave* w;
@@ -335,7 +358,7 @@ struct Ctx {
   float *rreg, *rssd, *eta, *prev;
   float *st, *vs, *u, *u2, *ab, *sc, *vb, *psi;
   long long ntot;
-  Prof* prof;
+  std::vector<Launch>* rec;  // when set, launches are recorded here instead of issued
 };
 
 Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
@@ -355,7 +378,7 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   c.rssd = (float*)(b + w.o_rssd);
   c.eta = (float*)(b + w.o_eta);
   c.prev = (float*)(b + w.o_prev);
-  char* f = b + p->header_total;
+  char* f = b + p->header_total + w.field_off;
   const Fields F = field_layout(p, w.ntot);
   c.st = (float*)(f + F.st); c.vs = (float*)(f + F.vs); c.u = (float*)(f + F.u); c.u2 = (float*)(f + F.u2);
   c.ab = (float*)(f + F.ab); c.sc = (float*)(f + F.sc); c.vb = (float*)(f + F.vb);
@@ -379,11 +402,14 @@ float* ST(const Ctx& c, int t) { return c.st + (size_t)st_slot(c.p, t) * 2 * c.n
 float* VS(const Ctx& c, int t) { return c.vs + (size_t)v_slot(c.p, t) * c.p->ndim * c.ntot; }
 float* AB(const Ctx& c, int t) { return c.ab + (size_t)(t & 1) * 2 * c.ntot; }
 
-#define LAUNCH(kid, expr)                       \
-  do {                                          \
-    ProfScope ps_(c.prof, c.s, kid);            \
-    hipError_t e_ = (expr);                     \
-    if (e_ != hipSuccess) return e_;            \
+#define LAUNCH(kid, expr)                                      \
+  do {                                                         \
+    if (c.rec) {                                               \
+      c.rec->push_back(Launch{kid, [=]() { return (expr); }}); \
+    } else {                                                   \
+      hipError_t e_ = (expr);                                  \
+      if (e_ != hipSuccess) return e_;                         \
+    }                                                          \
   } while (0)
 
 // v_t = -G (z_t grad I_t) into the v slot of t.
@@ -495,24 +521,110 @@ hipError_t run_grad(const Ctx& c) {
   return hipSuccess;
 }
 
-hipError_t enqueue(shoot_plan_s* p, int op, hipStream_t s) {
-  for (Wave& w : p->waves) {
-    Ctx c = make_ctx(p, w, s);
-    c.prof = p->profiling ? &p->prof : nullptr;
-    hipError_t e = is_grad(op) ? run_grad(c) : run_forward(c, op);
+// The whole schedule of one wave for `op` on stream s (recorded into `rec`
+// instead when given).
+hipError_t enqueue_wave(shoot_plan_s* p, Wave& w, int op, hipStream_t s, std::vector<Launch>* rec = nullptr) {
+  Ctx c = make_ctx(p, w, s);
+  c.rec = rec;
+  hipError_t e = is_grad(op) ? run_grad(c) : run_forward(c, op);
+  if (e != hipSuccess) return e;
+  if (op == OP_DESCEND || op == OP_DESCEND_RESET) {
+    const int reset = op == OP_DESCEND_RESET ? 1 : 0;
+    LAUNCH(KI_DESCEND, launch_descend(p->ndim, (int)w.pdev.size(), c.pd, c.tb, c.ntb, c.eta, c.prev, reset,
+                                      p->eta0, c.s));
+  }
+  return hipSuccess;
+}
+
+// Stream of lane i of a group whose lane 0 runs on s. Lane 1 takes the
+// capture stream, so a plan of L lanes holds L streams (each stream takes one
+// of the device's few hardware queues; lanes that shared one would run one
+// after the other).
+hipStream_t lane_stream(const shoot_plan_s* p, hipStream_t s, int i) {
+  return i == 0 ? s : (i == 1 ? p->cap : p->side[i - 2]);
+}
+
+// Fork: lanes 1 .. n-1 wait for the work already on s. Join: s waits for them.
+hipError_t fork_lanes(shoot_plan_s* p, hipStream_t s, int n) {
+  if (n < 2) return hipSuccess;
+  hipError_t e = hipEventRecord(p->ev_fork, s);
+  for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(lane_stream(p, s, i), p->ev_fork, 0);
+  return e;
+}
+hipError_t join_lanes(shoot_plan_s* p, hipStream_t s, int n) {
+  hipError_t e = hipSuccess;
+  for (int i = 1; i < n && e == hipSuccess; ++i) {
+    e = hipEventRecord(p->ev_join[i - 1], lane_stream(p, s, i));
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[i - 1], 0);
+  }
+  return e;
+}
+
+// Eager launches: every group's lanes concurrently (one after another on s
+// when `serial`, e.g. inside the caller's stream capture).
+hipError_t enqueue(shoot_plan_s* p, int op, hipStream_t s, bool serial) {
+  for (const auto& g : p->groups) {
+    const int n = serial ? 1 : g.second;
+    hipError_t e = fork_lanes(p, s, n);
     if (e != hipSuccess) return e;
-    if (op == OP_DESCEND || op == OP_DESCEND_RESET) {
-      const int reset = op == OP_DESCEND_RESET ? 1 : 0;
-      LAUNCH(KI_DESCEND, launch_descend(p->ndim, (int)w.pdev.size(), c.pd, c.tb, c.ntb, c.eta, c.prev, reset,
-                                        p->eta0, c.s));
+    for (int i = 0; i < g.second; ++i) {
+      e = enqueue_wave(p, p->waves[g.first + i], op, lane_stream(p, s, serial ? 0 : i));
+      if (e != hipSuccess) return e;
+    }
+    e = join_lanes(p, s, n);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Profiling: the lanes of a group run one after another on s, the k-th
+// launches of all lanes together between one event pair, so a timed launch
+// covers every pair of the group (as one launch over all of them would,
+// plus the extra launches' ramp and drain).
+hipError_t enqueue_profiled(shoot_plan_s* p, int op, hipStream_t s) {
+  for (const auto& g : p->groups) {
+    const int n = g.second;
+    std::vector<std::vector<Launch>> rec(n);
+    for (int i = 0; i < n; ++i) {
+      hipError_t e = enqueue_wave(p, p->waves[g.first + i], op, s, &rec[i]);
+      if (e != hipSuccess) return e;
+    }
+    for (int i = 1; i < n; ++i) {
+      if (rec[i].size() != rec[0].size()) return hipErrorInvalidValue;
+      for (size_t k = 0; k < rec[0].size(); ++k)
+        if (rec[i][k].kid != rec[0][k].kid) return hipErrorInvalidValue;
+    }
+    for (size_t k = 0; k < rec[0].size(); ++k) {
+      Prof::Rec r{rec[0][k].kid, p->prof.get(), p->prof.get()};
+      if (r.a) (void)hipEventRecord(r.a, s);
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < n && e == hipSuccess; ++i) e = rec[i][k].fn();
+      if (r.b) (void)hipEventRecord(r.b, s);
+      p->prof.pending.push_back(r);
+      if (e != hipSuccess) return e;
     }
   }
   return hipSuccess;
 }
 
-void drop_graphs(shoot_plan_s* p) {
-  for (auto& g : p->graph)
-    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+void release_streams(shoot_plan_s* p) {
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  p->cap = nullptr;
+  for (hipStream_t st : p->side) (void)hipStreamDestroy(st);
+  p->side.clear();
+  for (hipEvent_t ev : p->ev_join) (void)hipEventDestroy(ev);
+  p->ev_join.clear();
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  p->ev_fork = nullptr;
+}
+
+void drop_graphs(shoot_plan_s* p, int only_op = -1) {
+  for (int op = 0; op < OP_N; ++op) {
+    if (only_op >= 0 && op != only_op) continue;
+    for (hipGraphExec_t g : p->graph[op])
+      if (g) (void)hipGraphExecDestroy(g);
+    p->graph[op].clear();
+  }
 }
 
 shoot_status execute(shoot_plan_s* p, int op, void* stream) {
@@ -540,7 +652,7 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
   if (s) HIPCHK(hipStreamIsCapturing(s, &cs));
   if (p->profiling) {
     if (cs != hipStreamCaptureStatusNone) return fail(SHOOT_E_STATE, "profiling cannot run under stream capture");
-    hipError_t e = enqueue(p, op, s);
+    hipError_t e = enqueue_profiled(p, op, s);
     hipError_t e2 = hipStreamSynchronize(s);
     hipError_t e3 = p->prof.resolve();
     if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -549,27 +661,36 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
     return SHOOT_OK;
   }
   if ((p->flags & SHOOT_NO_GRAPH) || cs != hipStreamCaptureStatusNone) {
-    hipError_t e = enqueue(p, op, s);
+    // inside the caller's capture the lanes stay on its stream
+    hipError_t e = enqueue(p, op, s, cs != hipStreamCaptureStatusNone);
     if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SHOOT_OK;
   }
-  if (!p->graph[op]) {
-    HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
-    hipError_t e = enqueue(p, op, p->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(p->cap, &g);
-    if (e != hipSuccess) {
+  // one graph per wave, captured on the plan's own stream at the first call
+  if (p->graph[op].empty()) {
+    std::vector<hipGraphExec_t> gs;
+    for (Wave& w : p->waves) {
+      HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+      hipError_t e = enqueue_wave(p, w, op, p->cap);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+      hipGraphExec_t x = nullptr;
+      if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
       if (g) (void)hipGraphDestroy(g);
-      return fail(SHOOT_E_HIP, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+      if (e != hipSuccess || e2 != hipSuccess) {
+        for (hipGraphExec_t y : gs) (void)hipGraphExecDestroy(y);
+        if (e2 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+        return fail(SHOOT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      }
+      gs.push_back(x);
     }
-    if (e2 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
-    hipGraphExec_t x = nullptr;
-    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    p->graph[op] = x;
+    p->graph[op] = gs;
   }
-  HIPCHK(hipGraphLaunch(p->graph[op], s));
+  for (const auto& g : p->groups) {
+    HIPCHK(fork_lanes(p, s, g.second));
+    for (int i = 0; i < g.second; ++i) HIPCHK(hipGraphLaunch(p->graph[op][g.first + i], lane_stream(p, s, i)));
+    HIPCHK(join_lanes(p, s, g.second));
+  }
   return SHOOT_OK;
 }
 
@@ -598,8 +719,9 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
   if (!out) return fail(SHOOT_E_ARG, "out is NULL");
   *out = nullptr;
   const uint32_t known = SHOOT_FULL_STORE | SHOOT_UNFUSED | SHOOT_NO_GRAPH | SHOOT_FORCE_GLOBAL_SCATTER |
-                         SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED;
+                         SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED | SHOOT_LANES_MASK;
   if (flags & ~known) return fail(SHOOT_E_ARG, "unknown flag bits");
+  if (((flags & SHOOT_LANES_MASK) >> 8) > SHOOT_MAX_LANES) return fail(SHOOT_E_ARG, "SHOOT_LANES(n) needs n <= 8");
   const uint32_t schemes = flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED);
   if (schemes == (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED))
     return fail(SHOOT_E_ARG, "SHOOT_SCHEME_EULERIAN and SHOOT_SCHEME_MIXED exclude each other");
@@ -638,34 +760,47 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     g_err.clear();
     return SHOOT_OK;
   }
-  // admission: first-fit in order into waves whose field region fits the budget
-  std::vector<Wave> waves;
-  Wave cur;
-  for (int i = 0; i < n_pairs; ++i) {
-    Wave trial = cur;
-    trial.ids.push_back(i);
-    build_wave(p, trial);
-    if (budget_bytes && !cur.ids.empty() && trial.field_bytes > budget_bytes) {
-      waves.push_back(cur);
-      cur = Wave();
-      cur.ids.push_back(i);
-      build_wave(p, cur);
-    } else {
-      cur = trial;
-    }
-    if (budget_bytes && cur.ids.size() == 1 && cur.field_bytes > budget_bytes) {
-      delete p;
-      return fail(SHOOT_E_BUDGET, "pair " + std::to_string(i) + " alone needs " +
-                                      std::to_string(cur.field_bytes) + " bytes, over the budget");
+  // admission: first-fit in order into groups whose field region fits the
+  // budget; each group is split into concurrent lanes
+  const int want = (int)((flags & SHOOT_LANES_MASK) >> 8);
+  const int lanes = want ? want : (p->ndim == 2 ? 3 : 2);
+  std::vector<int> cur;
+  std::vector<Wave> lw;
+  size_t fb = 0;
+  auto commit = [&]() {
+    p->groups.emplace_back((int)p->waves.size(), (int)lw.size());
+    p->lanes = std::max(p->lanes, (int)lw.size());
+    p->field_max = std::max(p->field_max, fb);
+    for (Wave& w : lw) p->waves.push_back(w);
+  };
+  if (!budget_bytes) {
+    for (int i = 0; i < n_pairs; ++i) cur.push_back(i);
+    fb = build_group(p, cur, lanes, lw);
+  } else {
+    for (int i = 0; i < n_pairs; ++i) {
+      std::vector<int> trial = cur;
+      trial.push_back(i);
+      std::vector<Wave> tw;
+      const size_t tb = build_group(p, trial, lanes, tw);
+      if (!cur.empty() && tb > budget_bytes) {
+        commit();
+        cur.assign(1, i);
+        fb = build_group(p, cur, lanes, lw);
+      } else {
+        cur = trial;
+        lw = tw;
+        fb = tb;
+      }
+      if (cur.size() == 1 && fb > budget_bytes) {
+        delete p;
+        return fail(SHOOT_E_BUDGET, "pair " + std::to_string(i) + " alone needs " + std::to_string(fb) +
+                                        " bytes, over the budget");
+      }
     }
   }
-  waves.push_back(cur);
-  p->waves = waves;
+  commit();
   size_t o = 0;
-  for (Wave& w : p->waves) {
-    o = header_size(p, w, o);
-    p->field_max = std::max(p->field_max, w.field_bytes);
-  }
+  for (Wave& w : p->waves) o = header_size(p, w, o);
   p->header_total = align_up(o, ALIGN);
   p->ws_bytes = p->header_total + p->field_max;
   // host image of the header
@@ -695,7 +830,13 @@ shoot_status shoot_plan_workspace_bytes(shoot_plan p, size_t* bytes) {
 
 shoot_status shoot_plan_waves(shoot_plan p, int32_t* waves) {
   if (!p || !waves) return fail(SHOOT_E_ARG, "NULL argument");
-  *waves = p->uf ? p->npairs : (int32_t)p->waves.size();
+  *waves = p->uf ? p->npairs : (int32_t)p->groups.size();
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_lanes(shoot_plan p, int32_t* lanes) {
+  if (!p || !lanes) return fail(SHOOT_E_ARG, "NULL argument");
+  *lanes = p->uf ? 1 : p->lanes;
   return SHOOT_OK;
 }
 
@@ -708,11 +849,19 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
   int dev = -1;
   HIPCHK(hipGetDevice(&dev));
   drop_graphs(p);
-  if (p->cap && dev != p->device) {
-    (void)hipStreamDestroy(p->cap);
-    p->cap = nullptr;
-  }
+  if (dev != p->device) release_streams(p);
   if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+  while ((int)p->side.size() < p->lanes - 2) {
+    hipStream_t st = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    p->side.push_back(st);
+  }
+  while ((int)p->ev_join.size() < p->lanes - 1) {
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    p->ev_join.push_back(ev);
+  }
+  if (p->lanes > 1 && !p->ev_fork) HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
   p->device = dev;
   p->ws = (char*)workspace;
   p->descend_ready = false;
@@ -806,10 +955,7 @@ shoot_status shoot_descend(shoot_plan p, float eta0, int32_t reset, void* stream
   if (p->uf) return fail(SHOOT_E_ARG, "descent is not available on the unfused path");
   if (reset) {
     if (!(eta0 > 0.f) || !std::isfinite(eta0)) return fail(SHOOT_E_ARG, "eta0 must be finite and > 0");
-    if (eta0 != p->eta0 && p->graph[OP_DESCEND_RESET]) {
-      (void)hipGraphExecDestroy(p->graph[OP_DESCEND_RESET]);
-      p->graph[OP_DESCEND_RESET] = nullptr;
-    }
+    if (eta0 != p->eta0) drop_graphs(p, OP_DESCEND_RESET);
     p->eta0 = eta0;
   } else if (!p->descend_ready) {
     return fail(SHOOT_E_STATE, "the first shoot_descend call after a bind must reset");
@@ -846,7 +992,7 @@ shoot_status shoot_plan_destroy(shoot_plan p) {
   if (!p) return SHOOT_OK;
   drop_graphs(p);
   p->prof.release();
-  if (p->cap) (void)hipStreamDestroy(p->cap);
+  release_streams(p);
   if (p->uf) unfused::destroy(p->uf);
   delete p;
   return SHOOT_OK;

@@ -121,6 +121,64 @@ def test_budget_splits_into_waves():
     assert st == _lib.SHOOT_E_BUDGET
 
 
+def test_lanes_flag_and_count():
+    lib = _lib.load()
+    n = ctypes.c_int32()
+    pairs2 = [pair(shape=(96 + 8 * i, 64)) for i in range(6)]
+    # default: 3 lanes in 2-D, at most one per pair; 2 in 3-D
+    st, h = create(pairs2)
+    assert st == _lib.SHOOT_OK and lib.shoot_plan_lanes(h, ctypes.byref(n)) == _lib.SHOOT_OK and n.value == 3
+    lib.shoot_plan_destroy(h)
+    st, h = create(pairs2[:2])
+    lib.shoot_plan_lanes(h, ctypes.byref(n))
+    assert n.value == 2
+    lib.shoot_plan_destroy(h)
+    st, h = create([pair(ndim=3, shape=(16, 16, 16)) for _ in range(5)])
+    lib.shoot_plan_lanes(h, ctypes.byref(n))
+    assert n.value == 2
+    lib.shoot_plan_destroy(h)
+    # fixed counts; the workspace hardly depends on them (lane alignment only)
+    sizes = {}
+    for k in (1, 2, 6):
+        st, h = create(pairs2, flags=_lib.SHOOT_LANES(k))
+        assert st == _lib.SHOOT_OK
+        lib.shoot_plan_lanes(h, ctypes.byref(n))
+        assert n.value == k
+        b = ctypes.c_size_t()
+        lib.shoot_plan_workspace_bytes(h, ctypes.byref(b))
+        sizes[k] = b.value
+        lib.shoot_plan_destroy(h)
+    assert max(sizes.values()) < 1.01 * min(sizes.values())
+    st, _ = create(pairs2, flags=_lib.SHOOT_LANES(9))
+    assert st == _lib.SHOOT_E_ARG
+    # unfused plans run pair by pair: one lane
+    st, h = create(pairs2, flags=_lib.SHOOT_UNFUSED)
+    lib.shoot_plan_lanes(h, ctypes.byref(n))
+    assert n.value == 1
+    lib.shoot_plan_destroy(h)
+    assert lib.shoot_plan_lanes(None, ctypes.byref(n)) == _lib.SHOOT_E_ARG
+
+
+def test_budget_counts_the_lanes_of_a_wave():
+    """Admission sizes a wave with its lanes: smaller budgets give more waves
+    and a smaller workspace."""
+    lib = _lib.load()
+    pairs = [pair(shape=(64 + 16 * (i % 3), 96)) for i in range(7)]
+    st, h = create(pairs, T=9)
+    full = ctypes.c_size_t()
+    lib.shoot_plan_workspace_bytes(h, ctypes.byref(full))
+    lib.shoot_plan_destroy(h)
+    for frac in (0.9, 0.6, 0.35):
+        budget = int(full.value * frac)
+        st, h = create(pairs, T=9, budget=budget)
+        assert st == _lib.SHOOT_OK
+        b, w = ctypes.c_size_t(), ctypes.c_int32()
+        lib.shoot_plan_workspace_bytes(h, ctypes.byref(b))
+        lib.shoot_plan_waves(h, ctypes.byref(w))
+        assert w.value >= 2 and b.value < full.value
+        lib.shoot_plan_destroy(h)
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_LIB", None)
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))

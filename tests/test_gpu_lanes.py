@@ -1,0 +1,92 @@
+"""Concurrent lanes: a batch split into lanes that run on their own streams
+gives exactly the outputs of the single-lane plan, through captured graphs,
+eager launches and the lockstep profiling mode, with and without admission
+waves."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as G
+from gpu_util import announce, host, specs
+from paper_2106_08817_amd import SHOOT_LANES, SHOOT_NO_GRAPH, Plan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    announce(request.node.nodeid)
+    yield
+
+
+def batch(ndim):
+    if ndim == 2:
+        shapes = [(40, 52), (67, 33), (96, 130), (30, 30), (75, 64), (52, 90), (33, 47)]
+        sig = [2.0, 3.3, 5.0, 1.2, 2.5, 4.0, 1.8]
+        T = 6
+    else:
+        shapes, sig, T = [(12, 17, 20), (9, 33, 14), (16, 16, 10)], [2.0, 1.5, 1.0], 4
+    pairs = [G.small_pair(s, seed=900 + i, rho=0.2 + 0.1 * i, sigma=sig[i], p0_kind="realistic", lam=0.01)
+             for i, s in enumerate(shapes)]
+    return pairs, T
+
+
+def outputs(plan, op):
+    getattr(plan, op)()
+    torch.cuda.synchronize()
+    out = [host(plan.out_cost).copy()]
+    for i in range(len(plan.out_image)):
+        out += [host(plan.out_image[i]).copy(), host(plan.out_momentum[i]).copy()]
+        if op == "grad":
+            out.append(host(plan.out_grad[i]).copy())
+    return out
+
+
+def assert_same(a, b, what):
+    assert len(a) == len(b)
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x, y), f"{what}: output {k} differs (max |d| {np.max(np.abs(x - y))})"
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_lanes_reproduce_the_single_lane_plan(ndim):
+    pairs, T = batch(ndim)
+    sp = specs(pairs)
+    one = Plan(sp, T, SHOOT_LANES(1))
+    assert one.lanes == 1
+    ref = {op: outputs(one, op) for op in ("grad", "forward")}
+    for k in ((2, 3, 4, 7) if ndim == 2 else (2, 3)):
+        for flags, mode in ((0, "graph"), (SHOOT_NO_GRAPH, "eager")):
+            announce(f"ndim {ndim} lanes {k} {mode}")
+            plan = Plan(sp, T, SHOOT_LANES(k) | flags)
+            assert plan.lanes == min(k, len(pairs))
+            for op in ("grad", "forward", "grad"):  # replays after another op
+                assert_same(outputs(plan, op), ref[op], f"{k} lanes, {mode}, {op}")
+            plan.close()
+
+
+def test_profiling_matches_and_counts_whole_batch_launches():
+    pairs, T = batch(2)
+    sp = specs(pairs)
+    ref = outputs(Plan(sp, T, SHOOT_LANES(1)), "grad")
+    stats = {}
+    for k in (1, 4):
+        plan = Plan(sp, T, SHOOT_LANES(k))
+        plan.set_profiling(True)
+        plan.reset_stats()
+        assert_same(outputs(plan, "grad"), ref, f"profiled, {k} lanes")
+        stats[k] = {name: n for name, (n, ms) in plan.kernel_stats().items()}
+        plan.set_profiling(False)
+        assert_same(outputs(plan, "grad"), ref, f"graph after profiling, {k} lanes")
+    # a timed launch covers every lane: the counts do not grow with lanes
+    assert stats[1] == stats[4]
+
+
+def test_admission_waves_with_lanes():
+    pairs, T = batch(2)
+    sp = specs(pairs)
+    ref = outputs(Plan(sp, T, SHOOT_LANES(1)), "grad")
+    full = Plan(sp, T).workspace_bytes
+    plan = Plan(sp, T, SHOOT_LANES(2), budget_bytes=int(0.6 * full))
+    assert plan.waves >= 2 and plan.lanes == 2
+    assert_same(outputs(plan, "grad"), ref, "waves of two lanes")
