@@ -129,10 +129,13 @@ typedef struct shoot_plan_s* shoot_plan;
  * identical whatever the lane count: pairs are independent and every pair's
  * arithmetic is the same. SHOOT_LANES(n), 1 <= n <= SHOOT_MAX_LANES, fixes the
  * count; without it a plan takes 3 lanes in 2-D and 2 in 3-D (at most one
- * lane per pair). A plan of n lanes uses n streams (the caller's and n - 1
- * of its own); lanes gain only while the device has a hardware queue for
- * each. Inside the caller's stream capture the lanes run one after another
- * on the caller's stream. */
+ * lane per pair). At the first bind on a device the library creates a pool
+ * of 3 lane streams and one graph-capture stream (more lane streams when a
+ * plan asks for more lanes), shared by all plans and kept until the process
+ * ends; lanes gain only while the device has a hardware queue for each lane
+ * stream. Plans share the pool, so the lanes of two plans called on
+ * different streams are ordered with each other. Inside the caller's stream
+ * capture the lanes run one after another on the caller's stream. */
 #define SHOOT_MAX_LANES 8
 #define SHOOT_LANES(n) ((((uint32_t)(n)) & 15u) << 8)
 #define SHOOT_LANES_MASK (15u << 8)

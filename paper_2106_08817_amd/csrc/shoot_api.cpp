@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -125,9 +126,8 @@ struct shoot_plan_s {
   std::vector<unsigned char> blob;  // header image uploaded at bind
   char* ws = nullptr;
   int device = -1;
-  hipStream_t cap = nullptr;
-  std::vector<hipStream_t> side;      // streams of lanes 2 .. lanes-1 (lane 0 runs on the caller's
-                                      // stream, lane 1 on cap, idle outside graph capture)
+  hipStream_t cap = nullptr;           // the device's capture stream (shared, not owned)
+  std::vector<hipStream_t> side;      // lane streams (the device's shared pool; lanes > 1)
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
   std::vector<hipGraphExec_t> graph[OP_N];  // per wave
@@ -536,26 +536,23 @@ hipError_t enqueue_wave(shoot_plan_s* p, Wave& w, int op, hipStream_t s, std::ve
   return hipSuccess;
 }
 
-// Stream of lane i of a group whose lane 0 runs on s. Lane 1 takes the
-// capture stream, so a plan of L lanes holds L streams (each stream takes one
-// of the device's few hardware queues; lanes that shared one would run one
-// after the other).
-hipStream_t lane_stream(const shoot_plan_s* p, hipStream_t s, int i) {
-  return i == 0 ? s : (i == 1 ? p->cap : p->side[i - 2]);
-}
+// Stream of lane i of a group of n lanes called on stream s: s itself for a
+// single lane, else the i-th stream of the device's lane pool.
+hipStream_t lane_stream(const shoot_plan_s* p, hipStream_t s, int n, int i) { return n < 2 ? s : p->side[i]; }
 
-// Fork: lanes 1 .. n-1 wait for the work already on s. Join: s waits for them.
+// Fork: the n lanes wait for the work already on s. Join: s waits for them.
 hipError_t fork_lanes(shoot_plan_s* p, hipStream_t s, int n) {
   if (n < 2) return hipSuccess;
   hipError_t e = hipEventRecord(p->ev_fork, s);
-  for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(lane_stream(p, s, i), p->ev_fork, 0);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->side[i], p->ev_fork, 0);
   return e;
 }
 hipError_t join_lanes(shoot_plan_s* p, hipStream_t s, int n) {
+  if (n < 2) return hipSuccess;
   hipError_t e = hipSuccess;
-  for (int i = 1; i < n && e == hipSuccess; ++i) {
-    e = hipEventRecord(p->ev_join[i - 1], lane_stream(p, s, i));
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[i - 1], 0);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = hipEventRecord(p->ev_join[i], p->side[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[i], 0);
   }
   return e;
 }
@@ -568,7 +565,7 @@ hipError_t enqueue(shoot_plan_s* p, int op, hipStream_t s, bool serial) {
     hipError_t e = fork_lanes(p, s, n);
     if (e != hipSuccess) return e;
     for (int i = 0; i < g.second; ++i) {
-      e = enqueue_wave(p, p->waves[g.first + i], op, lane_stream(p, s, serial ? 0 : i));
+      e = enqueue_wave(p, p->waves[g.first + i], op, lane_stream(p, s, n, i));
       if (e != hipSuccess) return e;
     }
     e = join_lanes(p, s, n);
@@ -607,10 +604,43 @@ hipError_t enqueue_profiled(shoot_plan_s* p, int op, hipStream_t s) {
   return hipSuccess;
 }
 
+// Streams of a device, shared by every plan of the process and kept until the
+// process ends: the lane pool and one capture stream. Each stream takes one of
+// the device's few hardware queues (handed out as streams are created, shared
+// once they run out), and lanes whose queues were shared with each other or
+// with the caller's stream would run one after the other; so the lane pool is
+// created first, at the first bind on the device, with DEFAULT_POOL streams.
+constexpr int DEFAULT_POOL = 3;
+struct DevStreams {
+  std::vector<hipStream_t> pool;
+  hipStream_t cap = nullptr;
+};
+std::mutex g_streams_mu;                 // guards g_streams
+std::mutex g_capture_mu;                 // one graph capture at a time on the shared capture stream
+std::vector<DevStreams> g_streams;       // [device]
+
+hipError_t device_streams(shoot_plan_s* p, int dev) {
+  std::lock_guard<std::mutex> lock(g_streams_mu);
+  if ((int)g_streams.size() <= dev) g_streams.resize(dev + 1);
+  DevStreams& d = g_streams[dev];
+  const int want = std::max(d.cap ? 0 : DEFAULT_POOL, p->lanes > 1 ? p->lanes : 0);
+  while ((int)d.pool.size() < want) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    d.pool.push_back(st);
+  }
+  if (!d.cap) {
+    hipError_t e = hipStreamCreateWithFlags(&d.cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  p->cap = d.cap;
+  p->side.assign(d.pool.begin(), d.pool.begin() + (p->lanes > 1 ? p->lanes : 0));
+  return hipSuccess;
+}
+
 void release_streams(shoot_plan_s* p) {
-  if (p->cap) (void)hipStreamDestroy(p->cap);
   p->cap = nullptr;
-  for (hipStream_t st : p->side) (void)hipStreamDestroy(st);
   p->side.clear();
   for (hipEvent_t ev : p->ev_join) (void)hipEventDestroy(ev);
   p->ev_join.clear();
@@ -666,12 +696,17 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
     if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return SHOOT_OK;
   }
-  // one graph per wave, captured on the plan's own stream at the first call
+  // one graph per wave, captured on the device's capture stream at the first call
   if (p->graph[op].empty()) {
+    std::lock_guard<std::mutex> lock(g_capture_mu);
     std::vector<hipGraphExec_t> gs;
     for (Wave& w : p->waves) {
-      HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
-      hipError_t e = enqueue_wave(p, w, op, p->cap);
+      hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) {
+        for (hipGraphExec_t y : gs) (void)hipGraphExecDestroy(y);
+        return fail(SHOOT_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+      }
+      e = enqueue_wave(p, w, op, p->cap);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(p->cap, &g);
       hipGraphExec_t x = nullptr;
@@ -688,7 +723,8 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
   }
   for (const auto& g : p->groups) {
     HIPCHK(fork_lanes(p, s, g.second));
-    for (int i = 0; i < g.second; ++i) HIPCHK(hipGraphLaunch(p->graph[op][g.first + i], lane_stream(p, s, i)));
+    for (int i = 0; i < g.second; ++i)
+      HIPCHK(hipGraphLaunch(p->graph[op][g.first + i], lane_stream(p, s, g.second, i)));
     HIPCHK(join_lanes(p, s, g.second));
   }
   return SHOOT_OK;
@@ -850,13 +886,8 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
   HIPCHK(hipGetDevice(&dev));
   drop_graphs(p);
   if (dev != p->device) release_streams(p);
-  if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
-  while ((int)p->side.size() < p->lanes - 2) {
-    hipStream_t st = nullptr;
-    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    p->side.push_back(st);
-  }
-  while ((int)p->ev_join.size() < p->lanes - 1) {
+  HIPCHK(device_streams(p, dev));
+  while ((int)p->ev_join.size() < p->lanes) {
     hipEvent_t ev = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     p->ev_join.push_back(ev);
