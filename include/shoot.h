@@ -136,6 +136,13 @@ typedef struct shoot_plan_s* shoot_plan;
  * stream. Plans share the pool, so the lanes of two plans called on
  * different streams are ordered with each other. Inside the caller's stream
  * capture the lanes run one after another on the caller's stream. */
+/* Input check: every execution call first counts, on the device, the
+ * non-finite values (NaN, Inf) of each pair's image, target and p0, reads the
+ * counts back (synchronising the stream; SHOOT_E_STATE under stream capture)
+ * and fails with SHOOT_E_ARG, naming the first such pair, before enqueueing
+ * anything else. Without it, non-finite inputs propagate into the outputs.
+ * Not available with SHOOT_UNFUSED. */
+#define SHOOT_CHECK_FINITE 64u
 #define SHOOT_MAX_LANES 8
 #define SHOOT_LANES(n) ((((uint32_t)(n)) & 15u) << 8)
 #define SHOOT_LANES_MASK (15u << 8)

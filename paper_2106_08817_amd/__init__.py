@@ -2,6 +2,7 @@
 image registration (arXiv:2106.08817): batched forward shooting, cost and a
 hand-written discrete adjoint (dH/dp0) behind a C ABI (include/shoot.h)."""
 from .api import (  # noqa: F401
+    SHOOT_CHECK_FINITE,
     SHOOT_FORCE_GLOBAL_SCATTER,
     SHOOT_FULL_STORE,
     SHOOT_LANES,

@@ -35,6 +35,7 @@ SHOOT_NO_GRAPH = 4
 SHOOT_FORCE_GLOBAL_SCATTER = 8
 SHOOT_SCHEME_EULERIAN = 16
 SHOOT_SCHEME_MIXED = 32
+SHOOT_CHECK_FINITE = 64
 SHOOT_MAX_LANES = 8
 SHOOT_LANES_MASK = 15 << 8
 

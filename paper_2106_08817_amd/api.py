@@ -19,11 +19,12 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (SHOOT_FORCE_GLOBAL_SCATTER, SHOOT_FULL_STORE, SHOOT_LANES, SHOOT_NO_GRAPH,  # noqa: F401
-                   SHOOT_SCHEME_EULERIAN, SHOOT_SCHEME_MIXED, SHOOT_UNFUSED, ShootError)
+from ._lib import (SHOOT_CHECK_FINITE, SHOOT_FORCE_GLOBAL_SCATTER, SHOOT_FULL_STORE, SHOOT_LANES,  # noqa: F401
+                   SHOOT_NO_GRAPH, SHOOT_SCHEME_EULERIAN, SHOOT_SCHEME_MIXED, SHOOT_UNFUSED, ShootError)
 
 __all__ = ["PairSpec", "Plan", "ShootCost", "shoot_cost", "gradient_descent",
-           "SHOOT_FULL_STORE", "SHOOT_UNFUSED", "SHOOT_NO_GRAPH", "SHOOT_FORCE_GLOBAL_SCATTER", "SHOOT_LANES"]
+           "SHOOT_FULL_STORE", "SHOOT_UNFUSED", "SHOOT_NO_GRAPH", "SHOOT_FORCE_GLOBAL_SCATTER", "SHOOT_LANES",
+           "SHOOT_CHECK_FINITE"]
 
 
 @dataclass

@@ -49,6 +49,8 @@ struct EpiArgs {
 
 hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s);
 hipError_t launch_init(int ndim, const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s);
+// cnt[pair] += number of non-finite values in the pair's image, target, p0.
+hipError_t launch_count_nonfinite(int ndim, const PairDev* pd, const Tile* tl, int nt, unsigned* cnt, hipStream_t s);
 hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* tl, int nt, size_t lds,
                         const float* src, float* dst, hipStream_t s);
 // rb: strided-pass outputs per thread (one of SPASS_RB); opt: tuning option

@@ -92,6 +92,35 @@ __global__ __launch_bounds__(NT) void k_init(const PairDev* __restrict__ pd, con
   }
 }
 
+// Count of the non-finite values of every pair's inputs (image, target when
+// given, p0) into cnt[pair], for the optional input check; cnt starts at 0.
+template <int NDIM>
+__global__ __launch_bounds__(NT) void k_count_nonfinite(const PairDev* __restrict__ pd,
+                                                        const Tile* __restrict__ tl, unsigned* __restrict__ cnt) {
+  using B = Blk<NDIM>;
+  __shared__ unsigned bc;
+  const Tile t = tl[xcd_tile(gridDim.x)];
+  const PairDev& P = pd[t.pair];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (threadIdx.x == 0) bc = 0u;
+  __syncthreads();
+  unsigned c = 0u;
+#pragma unroll
+  for (int k = 0; k < B::PPT; ++k) {
+    int lx, ly, lz;
+    B::local(threadIdx.x, k, lx, ly, lz);
+    if (t.a + lx >= nx || t.b + ly >= ny || t.c + lz >= nz) continue;
+    const unsigned idx = (unsigned)(((t.c + lz) * ny + (t.b + ly)) * nx + (t.a + lx));
+    // a value is finite when its magnitude compares <= FLT_MAX (false for NaN)
+    c += fabsf(gld(P.S, idx)) <= 3.402823466e38f ? 0u : 1u;
+    c += fabsf(gld(P.p0, idx)) <= 3.402823466e38f ? 0u : 1u;
+    if (P.J) c += fabsf(gld(P.J, idx)) <= 3.402823466e38f ? 0u : 1u;
+  }
+  if (c) atomicAdd(&bc, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && bc) atomicAdd(cnt + t.pair, bc);
+}
+
 // ----------------------------------------------------------------------------
 // Gaussian pass along x (the contiguous axis)
 // ----------------------------------------------------------------------------
@@ -1441,6 +1470,12 @@ hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s) 
   if (n <= 0) return hipSuccess;
   const long long nb = (n + NT - 1) / NT;
   k_fill_u32<<<(unsigned)(nb < 4096 ? nb : 4096), NT, 0, s>>>(p, n, v);
+  return post();
+}
+
+hipError_t launch_count_nonfinite(int ndim, const PairDev* pd, const Tile* tl, int nt, unsigned* cnt, hipStream_t s) {
+  if (ndim == 2) k_count_nonfinite<2><<<nt, NT, 0, s>>>(pd, tl, cnt);
+  else k_count_nonfinite<3><<<nt, NT, 0, s>>>(pd, tl, cnt);
   return post();
 }
 

@@ -56,7 +56,7 @@ struct Wave {
   size_t lds_x[2] = {0, 0}, lds_y[2] = {0, 0}, lds_z[2] = {0, 0};
   // header offsets (bytes from the workspace base)
   size_t o_pd = 0, o_tb = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
-  size_t o_dmax = 0, o_rreg = 0, o_rssd = 0, o_eta = 0, o_prev = 0;
+  size_t o_dmax = 0, o_rreg = 0, o_rssd = 0, o_eta = 0, o_prev = 0, o_nf = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
   size_t field_off = 0;  // of this lane's fields inside the field region
@@ -332,6 +332,7 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   w.o_rssd = take(w.tb.size() * sizeof(float));
   w.o_eta = take(w.pdev.size() * sizeof(float));
   w.o_prev = take(w.pdev.size() * sizeof(float));
+  w.o_nf = take(w.pdev.size() * sizeof(unsigned));
   w.header_bytes = o - base;
   return o;
 }
@@ -657,6 +658,29 @@ void drop_graphs(shoot_plan_s* p, int only_op = -1) {
   }
 }
 
+// SHOOT_CHECK_FINITE: counts the non-finite values of every pair's inputs on
+// the device, reads the counts back (synchronising s) and fails on the first
+// pair that has any, before any other work is enqueued.
+shoot_status check_finite(shoot_plan_s* p, hipStream_t s) {
+  std::vector<unsigned> cnt(p->npairs, 0u);
+  for (Wave& w : p->waves) {
+    unsigned* nf = (unsigned*)(p->ws + w.o_nf);
+    const PairDev* pd = (const PairDev*)(p->ws + w.o_pd);
+    const Tile* tb = (const Tile*)(p->ws + w.o_tb);
+    HIPCHK(launch_fill_u32(nf, (long long)w.pdev.size(), 0u, s));
+    HIPCHK(launch_count_nonfinite(p->ndim, pd, tb, (int)w.tb.size(), nf, s));
+    std::vector<unsigned> h(w.pdev.size());
+    HIPCHK(hipMemcpyAsync(h.data(), nf, h.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t li = 0; li < w.ids.size(); ++li) cnt[w.ids[li]] = h[li];
+  }
+  for (int i = 0; i < p->npairs; ++i)
+    if (cnt[i])
+      return fail(SHOOT_E_ARG, "pair " + std::to_string(i) + ": " + std::to_string(cnt[i]) +
+                                   " non-finite values in its image, target or p0");
+  return SHOOT_OK;
+}
+
 shoot_status execute(shoot_plan_s* p, int op, void* stream) {
   if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
   if (!p->ws) return fail(SHOOT_E_STATE, "plan is not bound to a workspace");
@@ -689,6 +713,12 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
     if (e2 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e2));
     if (e3 != hipSuccess) return fail(SHOOT_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e3));
     return SHOOT_OK;
+  }
+  if (p->flags & SHOOT_CHECK_FINITE) {
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(SHOOT_E_STATE, "SHOOT_CHECK_FINITE synchronises the stream: not allowed under stream capture");
+    shoot_status st = check_finite(p, s);
+    if (st != SHOOT_OK) return st;
   }
   if ((p->flags & SHOOT_NO_GRAPH) || cs != hipStreamCaptureStatusNone) {
     // inside the caller's capture the lanes stay on its stream
@@ -755,13 +785,15 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
   if (!out) return fail(SHOOT_E_ARG, "out is NULL");
   *out = nullptr;
   const uint32_t known = SHOOT_FULL_STORE | SHOOT_UNFUSED | SHOOT_NO_GRAPH | SHOOT_FORCE_GLOBAL_SCATTER |
-                         SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED | SHOOT_LANES_MASK;
+                         SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED | SHOOT_LANES_MASK | SHOOT_CHECK_FINITE;
   if (flags & ~known) return fail(SHOOT_E_ARG, "unknown flag bits");
   if (((flags & SHOOT_LANES_MASK) >> 8) > SHOOT_MAX_LANES) return fail(SHOOT_E_ARG, "SHOOT_LANES(n) needs n <= 8");
   const uint32_t schemes = flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED);
   if (schemes == (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED))
     return fail(SHOOT_E_ARG, "SHOOT_SCHEME_EULERIAN and SHOOT_SCHEME_MIXED exclude each other");
   if (schemes && (flags & SHOOT_UNFUSED)) return fail(SHOOT_E_ARG, "the unfused path integrates semi-Lagrangianly only");
+  if ((flags & SHOOT_CHECK_FINITE) && (flags & SHOOT_UNFUSED))
+    return fail(SHOOT_E_ARG, "SHOOT_CHECK_FINITE is not available with SHOOT_UNFUSED");
   if (flags & SHOOT_UNFUSED)
     for (int i = 0; i < n_pairs && pairs; ++i)
       if (pairs[i].out_deformation)

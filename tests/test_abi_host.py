@@ -179,6 +179,15 @@ def test_budget_counts_the_lanes_of_a_wave():
         lib.shoot_plan_destroy(h)
 
 
+def test_check_finite_flag_host_side():
+    lib = _lib.load()
+    st, h = create([pair()], flags=_lib.SHOOT_CHECK_FINITE)
+    assert st == _lib.SHOOT_OK
+    lib.shoot_plan_destroy(h)
+    st, _ = create([pair()], flags=_lib.SHOOT_CHECK_FINITE | _lib.SHOOT_UNFUSED)
+    assert st == _lib.SHOOT_E_ARG and b"SHOOT_CHECK_FINITE" in lib.shoot_last_error()
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_LIB", None)
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
