@@ -165,6 +165,14 @@ class Plan:
         """Cost and dH/dp0 of every pair (hand-written discrete adjoint)."""
         self._call(self._lib.shoot_grad_p0, "shoot_grad_p0", stream)
 
+    def cost_and_grad(self, stream=None):
+        """grad(), then (costs [n_pairs] = H of every pair, list of dH/dp0 per
+        pair): views of the plan's output tensors, valid until the next call."""
+        if self.out_cost is None or self.out_grad is None:
+            raise ValueError("cost_and_grad needs the 'cost' and 'grad' outputs")
+        self.grad(stream)
+        return self.out_cost[:, 0], list(self.out_grad)
+
     def descend(self, eta0: float = 1.0, reset: bool = False, stream=None) -> None:
         """One gradient-descent iteration on every pair's p0 (in place, on the
         device): cost and dH/dp0 at the current p0, then p0 -= eta_i dH/dp0,

@@ -1,0 +1,50 @@
+"""The Python API over the C ABI: the autograd Function and the batched
+convenience call give the plan's own results, which match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as G
+from gpu_util import announce, check_grad, dev, host, specs
+from paper_2106_08817_amd import Plan, ShootCost, shoot_cost
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    announce(request.node.nodeid)
+    yield
+
+
+def test_autograd_function_gives_the_adjoint_gradient():
+    p = G.small_pair((44, 36), 61, rho=0.4, sigma=2.2, p0_kind="realistic", lam=0.02)
+    T = 6
+    S, J = dev(p.source), dev(p.target)
+    p0 = dev(p.p0).requires_grad_(True)
+    H = ShootCost.apply(S, J, p0, p.rho, p.sigma, p.lam, T)
+    H.backward()
+    plan = Plan(specs([p]), T)
+    plan.grad()
+    torch.cuda.synchronize()
+    assert float(H) == float(plan.out_cost[0, 0])
+    assert np.array_equal(host(p0.grad), host(plan.out_grad[0]))
+    check_grad(plan, 0, p, T)
+    # the functional form, with an upstream weight
+    p0.grad = None
+    (3.0 * shoot_cost(S, J, p0, p.rho, p.sigma, p.lam, T)).backward()
+    assert np.array_equal(host(p0.grad), host(3.0 * plan.out_grad[0]))
+
+
+def test_cost_and_grad_returns_the_batch_outputs():
+    pairs = [G.small_pair(s, 70 + i, rho=0.3, sigma=1.8) for i, s in enumerate([(30, 41), (52, 28), (36, 36)])]
+    plan = Plan(specs(pairs), 4)
+    costs, grads = plan.cost_and_grad()
+    torch.cuda.synchronize()
+    assert costs.shape == (3,) and len(grads) == 3
+    assert np.array_equal(host(costs), host(plan.out_cost[:, 0]))
+    for i, p in enumerate(pairs):
+        assert grads[i].shape == p.source.shape
+        check_grad(plan, i, p, 4)
+    with pytest.raises(ValueError):
+        Plan(specs(pairs), 4, outputs=("image",)).cost_and_grad()
