@@ -203,6 +203,21 @@ def time_evals(plan, n, torch):
     return start.elapsed_time(stop) / 1000.0
 
 
+def per_eval_ms(plan, n, torch):
+    """Median and minimum of n individually timed evaluations (events on the
+    stream around each graph replay)."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(n):
+        plan.grad()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(n))
+    return ms[n // 2], ms[0]
+
+
 def cpu_baseline(workload, seconds):
     """The oracle as it stands, single-threaded NumPy, on the first pairs of the
     workload until about `seconds` of work (at least one pair)."""
@@ -379,6 +394,7 @@ def measure(name, steps, warmup, profile_steps, flags, autotune, torch, api, syn
     torch.cuda.synchronize()
     secs = time_evals(plan, steps, torch)
     ms_per_step = 1000.0 * secs / steps
+    ms_median, ms_min = per_eval_ms(plan, min(max(steps, 1), 20), torch)
     value = vsteps * steps / secs
     costs = plan.out_cost[:, 0].cpu().numpy()
     assert np.all(np.isfinite(costs)), "non-finite cost"
@@ -425,7 +441,7 @@ def measure(name, steps, warmup, profile_steps, flags, autotune, torch, api, syn
     out = {"pairs": len(wl.pairs), "voxels": voxels, "T": wl.T, "voxel_steps": vsteps, "value": value,
            "unit": "voxel-steps/s", "ms_per_eval": ms_per_step, "secs": secs,
            "pair_evals_per_s": len(wl.pairs) * steps / secs, "steps": steps, "tuning": tuning,
-           "lanes": plan.lanes,
+           "lanes": plan.lanes, "ms_per_eval_median": ms_median, "ms_per_eval_min": ms_min,
            "step_algorithmic_GBps": step_bytes / (ms_per_step / 1000.0) / 1e9,
            "step_hbm_frac": step_bytes / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBPS,
            "step_bytes": step_bytes, "roofline": roofline, "kernels": kernels}
@@ -568,6 +584,8 @@ def main():
                            "HIP graph each), sqrt(T) checkpoints",
                    "tuning": tuning},
         "pair_evals_per_s": main_run["pair_evals_per_s"],
+        "ms_per_step_median": main_run["ms_per_eval_median"],
+        "ms_per_step_min": main_run["ms_per_eval_min"],
         "step_algorithmic_GBps": main_run["step_algorithmic_GBps"],
         "step_hbm_frac": main_run["step_hbm_frac"],
         "roofline": roofline,
