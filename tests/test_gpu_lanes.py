@@ -90,3 +90,32 @@ def test_admission_waves_with_lanes():
     plan = Plan(sp, T, SHOOT_LANES(2), budget_bytes=int(0.6 * full))
     assert plan.waves >= 2 and plan.lanes == 2
     assert_same(outputs(plan, "grad"), ref, "waves of two lanes")
+
+
+def test_calls_inside_the_callers_graph_capture():
+    """Captured in the caller's own graph (the lanes then run one after
+    another on the caller's stream); every replay, with eager work and
+    synchronisation between replays, gives the eager outputs."""
+    pairs, T = batch(2)
+    sp = specs(pairs)
+    ref = outputs(Plan(sp, T), "grad")
+    plan = Plan(sp, T)
+    assert plan.lanes == 3
+    outputs(plan, "grad")
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s):
+        plan.grad()
+    for rep in range(3):
+        announce(f"replay {rep}")
+        plan.out_cost.fill_(-1.0)
+        for t in plan.out_grad + plan.out_image + plan.out_momentum:
+            t.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [host(plan.out_cost).copy()]
+        for i in range(len(pairs)):
+            got += [host(plan.out_image[i]).copy(), host(plan.out_momentum[i]).copy(), host(plan.out_grad[i]).copy()]
+        assert_same(got, ref, f"replay {rep}")
