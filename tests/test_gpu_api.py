@@ -27,7 +27,7 @@ def test_autograd_function_gives_the_adjoint_gradient():
     plan = Plan(specs([p]), T)
     plan.grad()
     torch.cuda.synchronize()
-    assert float(H) == float(plan.out_cost[0, 0])
+    assert float(H.detach()) == float(plan.out_cost[0, 0])
     assert np.array_equal(host(p0.grad), host(plan.out_grad[0]))
     check_grad(plan, 0, p, T)
     # the functional form, with an upstream weight
