@@ -129,11 +129,11 @@ typedef struct shoot_plan_s* shoot_plan;
  * identical whatever the lane count: pairs are independent and every pair's
  * arithmetic is the same. SHOOT_LANES(n), 1 <= n <= SHOOT_MAX_LANES, fixes the
  * count; without it a plan takes 3 lanes in 2-D and 2 in 3-D (at most one
- * lane per pair). At the first bind on a device the library creates a pool
- * of 3 lane streams and one graph-capture stream (more lane streams when a
- * plan asks for more lanes), shared by all plans and kept until the process
- * ends; lanes gain only while the device has a hardware queue for each lane
- * stream. Plans share the pool, so the lanes of two plans called on
+ * lane per pair). The last lane runs on the caller's stream, the others on a
+ * pool of streams that the library creates at the first bind on a device (3
+ * lane streams, more when a plan asks for more lanes, then one graph-capture
+ * stream), shared by all plans and kept until the process ends; lanes gain
+ * only while the device has a hardware queue for each of their streams. Plans share the pool, so the lanes of two plans called on
  * different streams are ordered with each other. Inside the caller's stream
  * capture the lanes run one after another on the caller's stream. */
 /* Input check: every execution call first counts, on the device, the

@@ -127,7 +127,7 @@ struct shoot_plan_s {
   char* ws = nullptr;
   int device = -1;
   hipStream_t cap = nullptr;           // the device's capture stream (shared, not owned)
-  std::vector<hipStream_t> side;      // lane streams (the device's shared pool; lanes > 1)
+  std::vector<hipStream_t> side;      // streams of lanes 0 .. lanes-2 (the device's shared pool)
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
   std::vector<hipGraphExec_t> graph[OP_N];  // per wave
@@ -537,21 +537,24 @@ hipError_t enqueue_wave(shoot_plan_s* p, Wave& w, int op, hipStream_t s, std::ve
   return hipSuccess;
 }
 
-// Stream of lane i of a group of n lanes called on stream s: s itself for a
-// single lane, else the i-th stream of the device's lane pool.
-hipStream_t lane_stream(const shoot_plan_s* p, hipStream_t s, int n, int i) { return n < 2 ? s : p->side[i]; }
+// Stream of lane i of a group of n lanes called on stream s: the last lane
+// runs on s itself, lanes 0 .. n-2 on the device's lane pool; with n = 1
+// (one lane, or lanes run one after another) every lane runs on s.
+hipStream_t lane_stream(const shoot_plan_s* p, hipStream_t s, int n, int i) {
+  return (n < 2 || i == n - 1) ? s : p->side[i];
+}
 
-// Fork: the n lanes wait for the work already on s. Join: s waits for them.
+// Fork: the pool lanes wait for the work already on s. Join: s waits for them.
 hipError_t fork_lanes(shoot_plan_s* p, hipStream_t s, int n) {
   if (n < 2) return hipSuccess;
   hipError_t e = hipEventRecord(p->ev_fork, s);
-  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->side[i], p->ev_fork, 0);
+  for (int i = 0; i < n - 1 && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->side[i], p->ev_fork, 0);
   return e;
 }
 hipError_t join_lanes(shoot_plan_s* p, hipStream_t s, int n) {
   if (n < 2) return hipSuccess;
   hipError_t e = hipSuccess;
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
+  for (int i = 0; i < n - 1 && e == hipSuccess; ++i) {
     e = hipEventRecord(p->ev_join[i], p->side[i]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[i], 0);
   }
@@ -610,7 +613,8 @@ hipError_t enqueue_profiled(shoot_plan_s* p, int op, hipStream_t s) {
 // the device's few hardware queues (handed out as streams are created, shared
 // once they run out), and lanes whose queues were shared with each other or
 // with the caller's stream would run one after the other; so the lane pool is
-// created first, at the first bind on the device, with DEFAULT_POOL streams.
+// created first, at the first bind on the device, with DEFAULT_POOL streams
+// (the last lane of a group runs on the caller's stream).
 constexpr int DEFAULT_POOL = 3;
 struct DevStreams {
   std::vector<hipStream_t> pool;
@@ -624,7 +628,7 @@ hipError_t device_streams(shoot_plan_s* p, int dev) {
   std::lock_guard<std::mutex> lock(g_streams_mu);
   if ((int)g_streams.size() <= dev) g_streams.resize(dev + 1);
   DevStreams& d = g_streams[dev];
-  const int want = std::max(d.cap ? 0 : DEFAULT_POOL, p->lanes > 1 ? p->lanes : 0);
+  const int want = std::max(d.cap ? 0 : DEFAULT_POOL, p->lanes - 1);
   while ((int)d.pool.size() < want) {
     hipStream_t st = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -636,7 +640,7 @@ hipError_t device_streams(shoot_plan_s* p, int dev) {
     if (e != hipSuccess) return e;
   }
   p->cap = d.cap;
-  p->side.assign(d.pool.begin(), d.pool.begin() + (p->lanes > 1 ? p->lanes : 0));
+  p->side.assign(d.pool.begin(), d.pool.begin() + (p->lanes - 1));
   return hipSuccess;
 }
 
@@ -919,7 +923,7 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
   drop_graphs(p);
   if (dev != p->device) release_streams(p);
   HIPCHK(device_streams(p, dev));
-  while ((int)p->ev_join.size() < p->lanes) {
+  while ((int)p->ev_join.size() < p->lanes - 1) {
     hipEvent_t ev = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     p->ev_join.push_back(ev);
