@@ -488,7 +488,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): the pairs of a "
-              "batch are independent, and this build measures one GPU's share.", file=sys.stderr)
+              "batch are independent, and the benchmark measures one GPU's share of such a batch.", file=sys.stderr)
         sys.exit(2)
 
     import torch

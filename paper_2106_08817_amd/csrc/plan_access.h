@@ -1,4 +1,4 @@
-// Read access to a plan's pair descriptors for the drivers built on the
+// Read access to a plan's pair descriptors for the optimisers built on the
 // C ABI (not exported).
 #pragma once
 
