@@ -33,11 +33,14 @@
  * Memory and streams
  *   Every buffer the kernels touch is owned by the caller: inputs, outputs and
  *   one workspace. The library allocates no device memory. A plan owns host
- *   memory, a capture stream and (unless SHOOT_NO_GRAPH) captured HIP graphs.
- *   Device pointers must stay valid and unchanged from shoot_plan_bind to
+ *   memory, HIP events and (unless SHOOT_NO_GRAPH) captured HIP graphs, one
+ *   per lane; the library keeps, per device, a few streams shared by all plans
+ *   (lanes, graph capture; see SHOOT_LANES) until the process ends. Device
+ *   pointers must stay valid and unchanged from shoot_plan_bind to
  *   shoot_plan_destroy (graphs replay them). Streams are hipStream_t passed as
  *   void*; NULL means the null stream. Execution calls are asynchronous on the
- *   stream and never synchronise it.
+ *   stream and never synchronise it (except with SHOOT_CHECK_FINITE, or with
+ *   profiling enabled).
  *
  * Errors
  *   Every entry point returns a shoot_status. Arguments are validated on the
@@ -297,7 +300,8 @@ shoot_status shoot_plan_reset_stats(shoot_plan plan);
 shoot_status shoot_plan_kernel_stats(shoot_plan plan, int32_t index, const char** name, int64_t* launches,
                                      double* total_ms);
 
-/* Release the plan's host memory, capture stream and graphs. NULL is a no-op. */
+/* Release the plan's host memory, events and graphs (the shared streams
+ * stay). NULL is a no-op. */
 shoot_status shoot_plan_destroy(shoot_plan plan);
 
 #ifdef __cplusplus
