@@ -7,6 +7,7 @@ import torch
 import oracle
 import synthetic as G
 from gpu_util import announce, dev, host, rel, specs
+from golden_fixtures import fig1_steps
 from paper_2106_08817_amd import SHOOT_SCHEME_EULERIAN, SHOOT_SCHEME_MIXED, PairSpec, Plan, ShootError
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +47,8 @@ def test_stability_comparison_on_device():
     S, J, p0 = G.ripple_case()
     lo, hi = float(S.min()), float(S.max())
     out = {}
-    for name, flags, T in (("sl", 0, 20), ("eulerian", SHOOT_SCHEME_EULERIAN, 38)):
+    t_eul, t_sl = fig1_steps()
+    for name, flags, T in (("sl", 0, t_sl), ("eulerian", SHOOT_SCHEME_EULERIAN, t_eul)):
         plan = Plan([PairSpec(dev(S), dev(p0), 0.0, 3.0, 0.01, dev(J))], T, flags, outputs=("image", "cost"))
         plan.forward()
         torch.cuda.synchronize()

@@ -6,6 +6,9 @@ import pytest
 
 import oracle as O
 import synthetic as G
+from golden_fixtures import fig1_steps
+
+T_EUL, T_SL = fig1_steps()  # the paper's Fig. 1 time steps (tests/golden)
 
 
 @pytest.mark.parametrize("scheme", ["eulerian", "mixed"])
@@ -60,9 +63,9 @@ def test_eulerian_ripples_where_semi_lagrangian_does_not():
     advection semi-Lagrangian (mixed) keeps the image in range but its
     momentum ripples (far larger total variation than the full scheme's)."""
     S, J, p0 = G.ripple_case()
-    sl = O.shoot(S, p0, 0.0, 3.0, 20, scheme="sl")
-    eu = O.shoot(S, p0, 0.0, 3.0, 38, scheme="eulerian")
-    mx = O.shoot(S, p0, 0.0, 3.0, 20, scheme="mixed")
+    sl = O.shoot(S, p0, 0.0, 3.0, T_SL, scheme="sl")
+    eu = O.shoot(S, p0, 0.0, 3.0, T_EUL, scheme="eulerian")
+    mx = O.shoot(S, p0, 0.0, 3.0, T_SL, scheme="mixed")
     lo, hi = float(S.min()), float(S.max())
     over = lambda I: max(float(I.max()) - hi, lo - float(I.min()), 0.0)  # noqa: E731
     assert over(sl.I[-1]) == 0.0
@@ -77,7 +80,7 @@ def test_eulerian_integration_fails_where_semi_lagrangian_holds():
     within range."""
     S, J, p0 = G.ripple_case(amplitude=200.0)
     with np.errstate(all="ignore"):
-        eu = O.shoot(S, p0, 0.0, 3.0, 38, scheme="eulerian").I[-1]
-    sl = O.shoot(S, p0, 0.0, 3.0, 20, scheme="sl").I[-1]
+        eu = O.shoot(S, p0, 0.0, 3.0, T_EUL, scheme="eulerian").I[-1]
+    sl = O.shoot(S, p0, 0.0, 3.0, T_SL, scheme="sl").I[-1]
     assert not np.all(np.isfinite(eu))
     assert np.all(np.isfinite(sl)) and sl.max() <= S.max() and sl.min() >= S.min()

@@ -50,3 +50,10 @@ def test_lesion_lies_inside_the_phantom():
     peak = np.unravel_index(np.argmax(diff), diff.shape)
     assert 0.25 * 96 < peak[0] < 0.75 * 96 and 0.25 * 128 < peak[1] < 0.75 * 128
     np.testing.assert_array_equal(p.p0, 0.0)
+
+
+def test_golden_fixture_holds_the_papers_fig1_time_steps():
+    """The fixture states the paper's printed time steps: Eulerian 1/38,
+    semi-Lagrangian 1/20 (Results, Fig. 1)."""
+    from golden_fixtures import fig1_steps
+    assert fig1_steps() == (38, 20)
