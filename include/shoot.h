@@ -46,7 +46,13 @@
  *   Every entry point returns a shoot_status. Arguments are validated on the
  *   host before anything is enqueued; a failed call enqueues nothing.
  *   shoot_last_error() returns a thread-local message describing the last
- *   failure of the calling thread. NaN / Inf in the inputs propagate.
+ *   failure of the calling thread. NaN / Inf in the inputs propagate
+ *   (unless SHOOT_CHECK_FINITE).
+ *
+ * Threads
+ *   A plan must not be used by two threads at once. Different plans may be
+ *   used from different threads; the library's shared state (the per-device
+ *   streams, graph capture on the shared capture stream) is guarded by locks.
  */
 #ifndef SHOOT_H
 #define SHOOT_H
