@@ -28,8 +28,12 @@ Parity status of each function (what pins it; tests/test_oracle_*.py):
   the interior, first-order convergence of the Eulerian time stepping, and
   the stability behaviour the paper reports (Eulerian ripples and failure
   where the semi-Lagrangian scheme keeps the image in range).
-* energy: diagnostic only, parity unpinned (the paper gives no numbers).
-* gradient_descent: parity unpinned (driver; its steps are pinned above).
+* energy: a constant image (only rho ||z||^2 is left) and a unit impulse of
+  z on a ramp image (the product of the Gaussian's centre taps), closed forms.
+* gradient_descent: the closed form of descent on the quadratic cost of a
+  constant source at T = 1 (iterates, costs and every step halving). The
+  halving rule (halve the step when the cost at the current iterate exceeds
+  the previous one) is this library's convention; the paper names none.
 * lbfgs (oracle/lbfgs.py): two-loop recursion against the explicit BFGS
   inverse-Hessian product; convergence on a strictly convex quadratic.
 """

@@ -22,5 +22,7 @@ from .phantoms import (  # noqa: F401
     phantom_pair,
     ripple_case,
     workload,
+    workload_pair,
+    c5_shape_classes,
     small_pair,
 )

@@ -291,6 +291,47 @@ def small_pair(shape: Sequence[int], seed: int, rho: float = 0.5, sigma: float =
     return pair
 
 
+def _c3_pair(i: int, p0_kind: str) -> Pair:
+    rng = np.random.default_rng(3000 + i)
+    H = int(rng.choice(SIZES_2D))
+    W = int(rng.choice(SIZES_2D))
+    r = float(rng.uniform(0.05, 1.0))
+    s = float(rng.uniform(2.0, 6.0))
+    return phantom_pair((H, W), 3000 + i + 100000, r, s, p0_kind)
+
+
+def _c5_shape(i: int) -> Tuple[Tuple[int, int, int], float]:
+    rng = np.random.default_rng(5000 + i)
+    shp = SHAPES_3D[int(rng.integers(len(SHAPES_3D)))]
+    return shp, float(rng.uniform(0.1, 1.0))
+
+
+def _c5_pair(i: int, p0_kind: str) -> Pair:
+    shp, r = _c5_shape(i)
+    return phantom_pair(shp, 5000 + i + 100000, r, 4.0, p0_kind)
+
+
+def workload_pair(name: str, i: int, p0_kind: str = "realistic") -> Pair:
+    """Pair i of a batched workload ("c3" or "c5"), generated alone (the same
+    arrays as workload(name).pairs[i])."""
+    name = name.lower()
+    if name == "c3":
+        return _c3_pair(i, p0_kind)
+    if name == "c5":
+        return _c5_pair(i, p0_kind)
+    raise ValueError(f"workload {name!r} has no per-pair generator")
+
+
+def c5_shape_classes(n_pairs: int = 16) -> dict:
+    """{shape: index of its first volume} over the 3-D batch (shapes only,
+    no arrays are generated)."""
+    out = {}
+    for i in range(n_pairs):
+        shp = _c5_shape(i)[0]
+        out.setdefault(shp, i)
+    return out
+
+
 def workload(name: str, p0_kind: str = "realistic", n_pairs: Optional[int] = None,
              rho: Optional[float] = None) -> Workload:
     """The named workload (see the module docstring)."""
@@ -301,23 +342,11 @@ def workload(name: str, p0_kind: str = "realistic", n_pairs: Optional[int] = Non
         r = 0.5 if rho is None else rho
         return Workload("c2", [phantom_pair((240, 240), 2, r, 5.0, p0_kind)], 20)
     if name == "c3":
-        pairs = []
-        for i in range(64 if n_pairs is None else n_pairs):
-            rng = np.random.default_rng(3000 + i)
-            H = int(rng.choice(SIZES_2D))
-            W = int(rng.choice(SIZES_2D))
-            r = float(rng.uniform(0.05, 1.0))
-            s = float(rng.uniform(2.0, 6.0))
-            pairs.append(phantom_pair((H, W), 3000 + i + 100000, r, s, p0_kind))
+        pairs = [_c3_pair(i, p0_kind) for i in range(64 if n_pairs is None else n_pairs)]
         return Workload("c3", pairs, 20)
     if name == "c4":
         return Workload("c4", [phantom_pair((160, 192, 160), 4, 0.3, 4.0, p0_kind)], 15)
     if name == "c5":
-        pairs = []
-        for i in range(16 if n_pairs is None else n_pairs):
-            rng = np.random.default_rng(5000 + i)
-            shp = SHAPES_3D[int(rng.integers(len(SHAPES_3D)))]
-            r = float(rng.uniform(0.1, 1.0))
-            pairs.append(phantom_pair(shp, 5000 + i + 100000, r, 4.0, p0_kind))
+        pairs = [_c5_pair(i, p0_kind) for i in range(16 if n_pairs is None else n_pairs)]
         return Workload("c5", pairs, 15)
     raise ValueError(f"unknown workload {name!r}")
