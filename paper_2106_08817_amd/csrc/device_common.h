@@ -19,6 +19,21 @@ __device__ __forceinline__ void gst(float* __restrict__ base, unsigned i, float 
   *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (i << 2)) = v;
 }
 
+// Four consecutive floats at element i of a uniform base (one dwordx4 access).
+// The aligned form needs i to be a multiple of 4 and the base 16-byte aligned;
+// the unaligned form (4-byte alignment) serves shifted stencil neighbours.
+typedef float vf4u __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ vf4 gld4(const float* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const vf4*>(reinterpret_cast<const char*>(base) + (i << 2));
+}
+__device__ __forceinline__ vf4 gld4u(const float* __restrict__ base, unsigned i) {
+  const vf4u v = *reinterpret_cast<const vf4u*>(reinterpret_cast<const char*>(base) + (i << 2));
+  return vf4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void gst4(float* __restrict__ base, unsigned i, vf4 v) {
+  *reinterpret_cast<vf4*>(reinterpret_cast<char*>(base) + (i << 2)) = v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

@@ -127,9 +127,12 @@ __global__ __launch_bounds__(NT) void k_count_nonfinite(const PairDev* __restric
 //
 // A tile is a run of rows of one pair. Each row is staged in LDS with r zeros
 // in front and zeros behind (zero padding of G), stride L = 4 (G4 + ntap4),
-// G4 = ceil(nx / 4). A thread produces four consecutive outputs of one row; the
-// taps run in blocks of four (weights zero past 2r), so each block reads one
-// new aligned float4 of the row and does 16 FMAs.
+// G4 = ceil(nx / 4). When nx is a multiple of four the fill moves four
+// consecutive x per 16-byte access (the central difference's x neighbours by
+// the row shifted one element either way); otherwise it loads one element per
+// lane. A thread produces four consecutive outputs of one row; the taps run in
+// blocks of four (weights zero past 2r), so each block reads one new aligned
+// float4 of the row and does 16 FMAs.
 template <int NDIM, bool GRADMUL>
 __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst) {
@@ -144,6 +147,81 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   const int row0 = t.a, nrows = t.b;
   const int plane = nrows * L;
 
+  const float* __restrict__ I = src + (GRADMUL ? 2 : NDIM) * P.off;
+  const float* __restrict__ Z = I + N;
+  if ((nx & 3) == 0) {
+    // fill by 16-byte accesses (rows are 16-byte aligned): an item is four
+    // consecutive x of one row, XV items per thread with their loads in
+    // flight together; the x neighbours of the central difference come from
+    // the same row shifted by one element (clamped at the row's ends)
+    constexpr int XV = 2;
+    const int G = nx >> 2;
+    const int ni = nrows * G;
+    const bool vst = (r & 3) == 0;  // the row's first column is 16-byte aligned in LDS
+    for (int i0 = threadIdx.x; i0 < ni; i0 += XV * NT) {
+      vf4 m[XV][NDIM];
+      int lcol[XV];
+#pragma unroll
+      for (int u = 0; u < XV; ++u) {
+        const int i = min(i0 + u * NT, ni - 1);
+        const int rl = i / G;
+        const int x = 4 * (i - rl * G);
+        lcol[u] = i0 + u * NT < ni ? rl * L + r + x : -1;
+        const int row = row0 + rl;
+        const unsigned idx = (unsigned)(row * nx + x);
+        if (GRADMUL) {
+          const int y = row % ny;
+          const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
+          const vf4 zc = gld4(Z, idx);
+          const vf4 ic = gld4(I, idx);
+          const vf4 il = gld4u(I, x > 0 ? idx - 1u : idx);
+          const vf4 ir = gld4u(I, x + 4 < nx ? idx + 1u : idx);
+          const vf4 iu = gld4(I, idx + yu), id = gld4(I, idx - yd);
+          vf4 izu = ic, izd = ic;
+          if (NDIM == 3) {
+            const int z = row / ny;
+            const unsigned zu = (unsigned)up(z, nz, ny * nx), zd = (unsigned)dn(z, ny * nx);
+            izu = gld4(I, idx + zu);
+            izd = gld4(I, idx - zd);
+          }
+          const vf4 lm = x > 0 ? il : vf4{ic.x, ic.x, ic.y, ic.z};
+          const vf4 rp = x + 4 < nx ? ir : vf4{ic.y, ic.z, ic.w, ic.w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float zq = 0.5f * zc[k];
+            m[u][NDIM - 1][k] = zq * (rp[k] - lm[k]);
+            m[u][NDIM - 2][k] = zq * (iu[k] - id[k]);
+            if (NDIM == 3) m[u][0][k] = zq * (izu[k] - izd[k]);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < NDIM; ++c) m[u][c] = gld4(I, c * N + idx);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < XV; ++u) {
+        if (lcol[u] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < NDIM; ++c) {
+          float* dstl = lds + c * plane + lcol[u];
+          if (vst) {
+            *reinterpret_cast<vf4*>(dstl) = m[u][c];
+          } else {
+            dstl[0] = m[u][c].x; dstl[1] = m[u][c].y; dstl[2] = m[u][c].z; dstl[3] = m[u][c].w;
+          }
+        }
+      }
+    }
+    // zero padding: r columns in front of each row, the rest of the row behind
+    const int pad = L - nx;
+    for (int i = threadIdx.x; i < nrows * pad; i += NT) {
+      const int rl = i / pad;
+      const int k = i - rl * pad;
+      const int col = k < r ? k : nx + k;
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) lds[c * plane + rl * L + col] = 0.f;
+    }
+  } else {
   // fill: the tile is cut into segments of 64 columns of one row; wave w
   // takes segments w, w + 4, ... and issues the loads of XSEG of them at once
   // (clamped loads, zero outside the row)
@@ -151,8 +229,6 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nch = (L + 63) >> 6;
   const int nseg = nrows * nch;
-  const float* __restrict__ I = src + (GRADMUL ? 2 : NDIM) * P.off;
-  const float* __restrict__ Z = I + N;
   for (int sb = 0; sb < nseg; sb += XSEG * (NT / 64)) {
     float m[XSEG][NDIM];
     int lcol[XSEG];
@@ -196,6 +272,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
       }
     }
   }
+  }
   __syncthreads();
 
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
@@ -238,18 +315,25 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
 // Gaussian pass along a strided axis (y, or z in 3-D)
 // ----------------------------------------------------------------------------
 //
-// A tile is 64 consecutive x (one per lane) x SEG = 4 RB outputs along the
-// pass axis at one index of the third axis, for the channel blockIdx.y. The
-// input is staged in LDS as (SEG + 4 ntap4) rows x 64 floats; LDS row j holds
-// the input at s = s0 - r + j. Each thread produces RB consecutive outputs.
+// A tile is 64 consecutive x x SEG = 4 RB outputs along the pass axis at one
+// index of the third axis, for the channel blockIdx.y. The input is staged in
+// LDS as (SEG + 4 ntap4) rows x 64 floats; LDS row j holds the input at
+// s = s0 - r + j. The block is 16 column groups (four consecutive x, moved as
+// one dwordx4 access) x 16 row groups; a thread produces RB / 4 consecutive
+// outputs along the axis for its four columns, reading the LDS window as
+// aligned 16-byte vectors. Every output sums its taps in blocks of four in the
+// same order whatever RB is.
 // MODE 0: plain pass. MODE 1: negated (v = -G m). MODE 2: negated, plus
 // -2 lambda * extra (the regulariser's cotangent at t = 0).
 template <int NDIM, bool PASSZ, int MODE, int RB>
 __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst,
                                               const float* __restrict__ extra) {
+  constexpr int RQ = RB / 4;      // outputs per thread along the axis
+  constexpr int SEG = 16 * RQ;    // outputs per tile along the axis
+  constexpr int FU = 4;           // fill loads per thread in flight per round
+  static_assert(SEG == (NT / 64) * RB, "tile geometry");
   extern __shared__ vf4 smem4[];
-  float* lds = reinterpret_cast<float*>(smem4);
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
   const int nx = P.nx, ny = P.ny, nz = P.nz, r = P.r, ntap4 = P.ntap4;
@@ -258,51 +342,71 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   const int ns = PASSZ ? nz : ny;
   const unsigned ss = (unsigned)(PASSZ ? ny * nx : nx);
   const unsigned so = (unsigned)(PASSZ ? nx : ny * nx);
-  const int lane = threadIdx.x & 63;
-  // wave-uniform, so the row of every fill load and its range test are scalar
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x = t.a + lane;
+  const int cg = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const int x = t.a + 4 * cg;
   const bool xin = x < nx;
+  const bool vec = (nx & 3) == 0;   // rows are 16-byte aligned: whole dwordx4 accesses
   const int s0 = t.c;
-  const int rows = (NT / 64) * RB + 4 * ntap4;
+  const int rows = SEG + 4 * ntap4;
   const int c = blockIdx.y;  // one channel per block
-  const unsigned base = (unsigned)t.b * so + (unsigned)min(x, nx - 1);
+  const unsigned base = (unsigned)t.b * so;
   const float* __restrict__ Fc = src + NDIM * P.off + c * N;
 
-  // fill: clamped loads, SFILL rows per thread in flight; rows outside the
-  // axis and lanes beyond nx are zeroed when stored
-  for (int j0 = wv; j0 < rows; j0 += SFILL * (NT / 64)) {
-    float v[SFILL];
+  // fill: clamped loads, FU rows per thread in flight per round; rows outside
+  // the axis and columns beyond nx are zeroed when stored
+  for (int j0 = rg; j0 < rows; j0 += FU * 16) {
+    vf4 v[FU];
 #pragma unroll
-    for (int u = 0; u < SFILL; ++u) {
-      const int s = s0 - r + j0 + u * (NT / 64);
-      v[u] = gld(Fc, base + (unsigned)clampi(s, 0, ns - 1) * ss);
+    for (int u = 0; u < FU; ++u) {
+      const int j = j0 + 16 * u;
+      const unsigned rowi = base + (unsigned)clampi(s0 - r + j, 0, ns - 1) * ss;
+      if (j < rows) {
+        if (vec) {
+          v[u] = gld4(Fc, rowi + (unsigned)min(x, nx - 4));
+        } else {
+          v[u] = vf4{gld(Fc, rowi + (unsigned)min(x, nx - 1)), gld(Fc, rowi + (unsigned)min(x + 1, nx - 1)),
+                     gld(Fc, rowi + (unsigned)min(x + 2, nx - 1)), gld(Fc, rowi + (unsigned)min(x + 3, nx - 1))};
+        }
+      }
     }
 #pragma unroll
-    for (int u = 0; u < SFILL; ++u) {
-      const int j = j0 + u * (NT / 64);
+    for (int u = 0; u < FU; ++u) {
+      const int j = j0 + 16 * u;
       const int s = s0 - r + j;
-      if (j < rows) lds[j * 64 + lane] = (xin && s >= 0 && s < ns) ? v[u] : 0.f;
+      if (j < rows) {
+        const bool in = s >= 0 && s < ns;
+        vf4 w = v[u];
+        w.x = (in && x < nx) ? w.x : 0.f;
+        w.y = (in && x + 1 < nx) ? w.y : 0.f;
+        w.z = (in && x + 2 < nx) ? w.z : 0.f;
+        w.w = (in && x + 3 < nx) ? w.w : 0.f;
+        smem4[j * 16 + cg] = w;
+      }
     }
   }
   __syncthreads();
 
-  float acc[RB];
+  vf4 acc[RQ];
 #pragma unroll
-  for (int i = 0; i < RB; ++i) acc[i] = 0.f;
+  for (int i = 0; i < RQ; ++i) acc[i] = vf4{0.f, 0.f, 0.f, 0.f};
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
-  const float* col = lds + (wv * RB) * 64 + lane;
+  const vf4* col = smem4 + (rg * RQ) * 16 + cg;
   for (int b = 0; b < ntap4; ++b) {
     const float4 w = W4[b];
-    float win[RB + 3];
+    vf4 win[RQ + 3];
 #pragma unroll
-    for (int j = 0; j < RB + 3; ++j) win[j] = col[(4 * b + j) * 64];
+    for (int j = 0; j < RQ + 3; ++j) win[j] = col[(4 * b + j) * 16];
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      acc[i] = fmaf(w.x, win[i], acc[i]);
-      acc[i] = fmaf(w.y, win[i + 1], acc[i]);
-      acc[i] = fmaf(w.z, win[i + 2], acc[i]);
-      acc[i] = fmaf(w.w, win[i + 3], acc[i]);
+    for (int i = 0; i < RQ; ++i) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float a = acc[i][k];
+        a = fmaf(w.x, win[i][k], a);
+        a = fmaf(w.y, win[i + 1][k], a);
+        a = fmaf(w.z, win[i + 2][k], a);
+        a = fmaf(w.w, win[i + 3][k], a);
+        acc[i][k] = a;
+      }
     }
   }
   if (xin) {
@@ -310,14 +414,29 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
     const float* __restrict__ Ec = (MODE == 2 && extra != nullptr) ? extra + NDIM * P.off + c * N : nullptr;
     const float escale = -2.f * P.lam;
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      const int s = s0 + wv * RB + i;
+    for (int i = 0; i < RQ; ++i) {
+      const int s = s0 + rg * RQ + i;
       if (s < ns) {
-        const unsigned idx = base + (unsigned)s * ss;
-        float o = acc[i];
+        const unsigned idx = base + (unsigned)s * ss + (unsigned)x;
+        vf4 o = acc[i];
         if (MODE >= 1) o = -o;
-        if (MODE == 2 && Ec != nullptr) o = fmaf(escale, gld(Ec, idx), o);
-        gst(Dc, idx, o);
+        if (vec) {
+          if (MODE == 2 && Ec != nullptr) {
+            const vf4 e = gld4(Ec, idx);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = fmaf(escale, e[k], o[k]);
+          }
+          gst4(Dc, idx, o);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (x + k < nx) {
+              float ok = o[k];
+              if (MODE == 2 && Ec != nullptr) ok = fmaf(escale, gld(Ec, idx + k), ok);
+              gst(Dc, idx + k, ok);
+            }
+          }
+        }
       }
     }
   }

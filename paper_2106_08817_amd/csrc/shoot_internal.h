@@ -14,12 +14,10 @@ constexpr int WPAD = 4 * ((2 * RMAX + 1 + 3) / 4);   // 64
 
 // Threads per block for every kernel.
 constexpr int NT = 256;
-// Strided-pass tile: 64 lanes along x, NT/64 waves along the pass axis, each
-// thread produces RB consecutive outputs along it (RB is a tuning option).
+// Strided-pass tile: 64 columns along x x (NT/64) RB outputs along the pass
+// axis (RB is a tuning option); a thread produces RB/4 outputs along the axis
+// for four consecutive columns.
 constexpr int SPASS_RB[2] = {16, 8};
-// Rows per thread whose loads the strided pass's fill keeps in flight at once
-// (one batch covers tiles up to radius 15).
-constexpr int SFILL = 24;
 // x-pass: 64-column segments per wave whose loads are in flight at once; the
 // host sizes x-pass tiles so one batch fills a tile where the row allows.
 constexpr int XSEG = 6;

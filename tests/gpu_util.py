@@ -100,3 +100,22 @@ def compare_grad(plan, i, H, g):
     assert eg <= GRAD_ELEM_TOL, ("grad element", eg)
     assert rH <= COST_TOL, ("cost", rH)
     return rg, rH
+
+
+def compare_adjoint_term(plan, i, pair, H, g):
+    """Pair i against the oracle through the adjoint term of the gradient.
+    dH/dp0 = zbar_0 + 2 lambda rho p0 (Eq. 4): at a momentum where descent
+    has converged the two terms cancel, and the sum is rounding noise of both;
+    the parity bound then applies to zbar_0, the adjoint's own output, taken
+    from either gradient by subtracting the regulariser term in float64."""
+    gg = host(plan.out_grad[i])
+    reg = 2.0 * pair.lam * pair.rho * np.asarray(pair.p0, dtype=np.float64)
+    zg, zo = gg - reg, np.asarray(g, dtype=np.float64) - reg
+    rz, ez = rel(zg, zo), elem(zg, zo)
+    rH = abs(float(plan.out_cost[i, 0]) - H) / abs(H)
+    announce(f"  adjoint term pair {i}: rel {rz:.2e} elem {ez:.2e} (|dH/dp0| / |zbar_0| = "
+             f"{np.linalg.norm(g) / max(np.linalg.norm(zo), 1e-300):.2e}); cost {rH:.2e}")
+    assert rz <= GRAD_TOL, ("adjoint term", rz)
+    assert ez <= GRAD_ELEM_TOL, ("adjoint term element", ez)
+    assert rH <= COST_TOL, ("cost", rH)
+    return rz, rH

@@ -87,9 +87,24 @@ def started() -> bool:
 
 
 def result(key, timeout=900):
+    """The oracle's result for `key`, waited for with a progress line every
+    30 s (a wait of minutes on a large volume is not a hang)."""
+    import sys
+    import time
+    from multiprocessing import TimeoutError as PoolTimeout
+
     if _pool is None:
         raise RuntimeError("the oracle pool was not started at collection")
-    return _pending[key].get(timeout)
+    t0 = time.monotonic()
+    while True:
+        left = timeout - (time.monotonic() - t0)
+        if left <= 0:
+            raise PoolTimeout(f"oracle job {key} not done after {timeout} s")
+        try:
+            return _pending[key].get(min(30.0, left))
+        except PoolTimeout:
+            sys.__stderr__.write(f"[gpu-case]   waiting for the oracle's {key} ({time.monotonic() - t0:.0f} s)\n")
+            sys.__stderr__.flush()
 
 
 def stop():

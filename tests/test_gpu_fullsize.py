@@ -8,7 +8,8 @@ size and full T on CPU workers (tests/oracle_pool.py) while the GPU tests run:
 * the 16-volume 3-D batch (T = 15) run whole, its first volume of each of the
   four shape classes compared with the oracle;
 * the 240x240 pair at the momentum the oracle's 200-iteration gradient descent
-  reached (the fourth kind of p0: after optimisation), for each rho.
+  reached (the fourth kind of p0: after optimisation), for each rho; there
+  the gradient's two terms cancel, so the adjoint term is compared.
 
 Gradients are compared in relative L2 and per element, costs relatively."""
 import numpy as np
@@ -17,8 +18,8 @@ import torch
 
 import oracle_pool
 import synthetic as G
-from gpu_util import (COST_TOL, GRAD_ELEM_TOL, GRAD_TOL, IMG_ELEM_TOL, IMG_TOL, announce, compare_grad, elem, host,
-                      rel, run, specs)
+from gpu_util import (COST_TOL, GRAD_ELEM_TOL, GRAD_TOL, IMG_ELEM_TOL, IMG_TOL, announce, compare_adjoint_term,
+                      compare_grad, elem, host, rel, run, specs)
 from golden_fixtures import c2_post_descent_p0
 from paper_2106_08817_amd import SHOOT_FULL_STORE, Plan
 
@@ -107,8 +108,10 @@ def test_c2_at_post_descent_momentum_matches_oracle(rho):
     plan.forward()
     torch.cuda.synchronize()
     H, g, I_T, z_T, D = oracle_pool.result(("c2", rho))
-    announce(f"  c2 rho {rho}: largest step displacement {D:.3f} px")
-    compare_grad(plan, 0, H, g)
+    announce(f"  c2 rho {rho}: largest step displacement {D:.4f} px")
+    # the descent converged (|dH/dp0| is ~1e-6 of its two terms at rho 1.0
+    # and 0.5): compare the adjoint term, not the cancelling sum
+    compare_adjoint_term(plan, 0, p, H, g)
     compare_forward(plan, 0, I_T, z_T, f"c2 rho {rho}")
 
 
