@@ -66,7 +66,7 @@ def bytes_per_voxel(name: str, d: int) -> int:
 # rocprofv3 kernel names -> kernel families of the profiling statistics
 def family_of(kernel_name: str) -> str:
     n = kernel_name
-    if "k_adv_adj_tile" in n:
+    if "k_adv_adj" in n:
         return "advect_adjoint"
     if "k_advect" in n:
         return "advect"

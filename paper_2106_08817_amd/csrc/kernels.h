@@ -59,6 +59,8 @@ hipError_t launch_spass(int ndim, bool passz, int mode, int rb, const PairDev* p
                         size_t lds, const float* src, float* dst, const float* extra, hipStream_t s);
 hipError_t launch_advect(int ndim, int opt, int nt, const AdvectArgs& a, hipStream_t s);
 hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream_t s);
+// 3-D adjoint of the advection over ADJ3 tiles (a.tl is the adjoint tile list).
+hipError_t launch_adv_adj3(int nt, const AdjArgs& a, hipStream_t s);
 hipError_t launch_epilogue(int ndim, int opt, int nt, const EpiArgs& a, hipStream_t s);
 hipError_t launch_finalize(int npairs, const PairDev* pd, const float* red_reg, const float* red_ssd,
                            hipStream_t s);

@@ -51,11 +51,12 @@ struct Wave {
   std::vector<int> ids;
   std::vector<PairDev> pdev;
   std::vector<Tile> tb;
+  std::vector<Tile> ta;                   // 3-D adjoint tiles (ADJ3)
   std::vector<Tile> tx[2], ty[2], tz[2];  // per tuning option of the x-pass / strided passes
   long long ntot = 0;                     // padded voxel total
   size_t lds_x[2] = {0, 0}, lds_y[2] = {0, 0}, lds_z[2] = {0, 0};
   // header offsets (bytes from the workspace base)
-  size_t o_pd = 0, o_tb = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
+  size_t o_pd = 0, o_tb = 0, o_ta = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
   size_t o_dmax = 0, o_rreg = 0, o_rssd = 0, o_eta = 0, o_prev = 0, o_nf = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
@@ -214,7 +215,7 @@ shoot_status validate(const shoot_pair* pairs, int32_t n, int32_t T) {
 
 // Builds descriptors and tile lists of one wave (header offsets are set later).
 void build_wave(shoot_plan_s* p, Wave& w) {
-  w.pdev.clear(); w.tb.clear();
+  w.pdev.clear(); w.tb.clear(); w.ta.clear();
   for (int o = 0; o < 2; ++o) {
     w.tx[o].clear(); w.ty[o].clear(); w.tz[o].clear();
     w.lds_x[o] = w.lds_y[o] = w.lds_z[o] = 0;
@@ -250,6 +251,11 @@ void build_wave(shoot_plan_s* p, Wave& w) {
           for (int x0 = 0; x0 < P.nx; x0 += BX) w.tb.push_back(Tile{pi, x0, y0, z0});
     }
     P.elem_count = (int)w.tb.size() - P.elem_first;
+    if (p->ndim == 3) {
+      for (int z0 = 0; z0 < P.nz; z0 += ADJ3_Z)
+        for (int y0 = 0; y0 < P.ny; y0 += ADJ3_Y)
+          for (int x0 = 0; x0 < P.nx; x0 += ADJ3_X) w.ta.push_back(Tile{pi, x0, y0, z0});
+    }
     // x-pass tiles: rows of the pair, at most as many as one batch of the fill
     // covers (XSEG 64-column segments per wave). Option 0: also at most one
     // group of four outputs per thread (nr * G4 <= NT), so the tap loop runs
@@ -322,6 +328,7 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, ALIGN); return r; };
   w.o_pd = take(w.pdev.size() * sizeof(PairDev));
   w.o_tb = take(w.tb.size() * sizeof(Tile));
+  w.o_ta = take(w.ta.size() * sizeof(Tile));
   for (int o = 0; o < 2; ++o) {
     w.o_tx[o] = take(w.tx[o].size() * sizeof(Tile));
     w.o_ty[o] = take(w.ty[o].size() * sizeof(Tile));
@@ -350,8 +357,8 @@ struct Ctx {
   Wave* w;
   hipStream_t s;
   const PairDev* pd;
-  const Tile *tb, *tx, *ty, *tz;
-  int ntb, ntx, nty, ntz;
+  const Tile *tb, *ta, *tx, *ty, *tz;
+  int ntb, nta, ntx, nty, ntz;
   size_t lds_x, lds_y, lds_z;
   int rb;                 // strided-pass outputs per thread
   int o_adv, o_adj, o_epi;  // load-batch options
@@ -368,6 +375,7 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   char* b = p->ws;
   c.pd = (const PairDev*)(b + w.o_pd);
   c.tb = (const Tile*)(b + w.o_tb); c.ntb = (int)w.tb.size();
+  c.ta = (const Tile*)(b + w.o_ta); c.nta = (int)w.ta.size();
   const int ox = p->tune[TUNE_XPASS], os = p->tune[TUNE_SPASS];
   c.tx = (const Tile*)(b + w.o_tx[ox]); c.ntx = (int)w.tx[ox].size(); c.lds_x = w.lds_x[ox];
   c.ty = (const Tile*)(b + w.o_ty[os]); c.nty = (int)w.ty[os].size(); c.lds_y = w.lds_y[os];
@@ -476,7 +484,12 @@ hipError_t bwd_step(const Ctx& c, int t) {
   a.pd = c.pd; a.tl = c.tb; a.V = VS(c, t); a.st = ST(c, t); a.ab_in = AB(c, t + 1);
   a.sc = c.sc; a.vb = c.vb;
   a.dmax = c.dmax; a.T = c.p->T; a.t = t; a.force_global = force;
-  LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.o_adj, c.ntb, a, c.s));
+  if (nd == 3) {
+    a.tl = c.ta;
+    LAUNCH(KI_ADV_ADJ, launch_adv_adj3(c.nta, a, c.s));
+  } else {
+    LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.o_adj, c.ntb, a, c.s));
+  }
   // mbar = -G vbar (+ -2 lambda v_0 at t = 0), written back into vb
   LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.lds_x, c.vb, c.u, c.s));
   const float* extra = t == 0 ? VS(c, 0) : nullptr;
@@ -883,6 +896,7 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     };
     put(w.o_pd, w.pdev.data(), w.pdev.size() * sizeof(PairDev));
     put(w.o_tb, w.tb.data(), w.tb.size() * sizeof(Tile));
+    put(w.o_ta, w.ta.data(), w.ta.size() * sizeof(Tile));
     for (int o = 0; o < 2; ++o) {
       put(w.o_tx[o], w.tx[o].data(), w.tx[o].size() * sizeof(Tile));
       put(w.o_ty[o], w.ty[o].data(), w.ty[o].size() * sizeof(Tile));

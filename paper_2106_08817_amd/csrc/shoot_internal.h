@@ -26,6 +26,10 @@ constexpr int XSEG = 6;
 // the per-step displacement bound is below BLK*_HS pixels.
 constexpr int BLK2_X = 32, BLK2_Y = 32, BLK2_HS = 2;
 constexpr int BLK3_X = 32, BLK3_Y = 8, BLK3_Z = 4, BLK3_HS = 1;
+// Tile of the 3-D adjoint of the advection (its own tile list): 16 x 8 x 8
+// outputs, a thread owns four consecutive x; fields are staged on the tile
+// grown by 2 along y and z and by 4 along x (whole 16-byte groups).
+constexpr int ADJ3_X = 16, ADJ3_Y = 8, ADJ3_Z = 8;
 // Voxels per load batch of the elementwise kernels (a batch's loads are in
 // flight together; larger batches trade registers, hence occupancy, for
 // memory-level parallelism per wave), per tuning option: [ndim - 2][option].

@@ -102,20 +102,32 @@ def compare_grad(plan, i, H, g):
     return rg, rH
 
 
-def compare_adjoint_term(plan, i, pair, H, g):
+def compare_adjoint_term(plan, i, pair, H, g, I_T):
     """Pair i against the oracle through the adjoint term of the gradient.
+
     dH/dp0 = zbar_0 + 2 lambda rho p0 (Eq. 4): at a momentum where descent
     has converged the two terms cancel, and the sum is rounding noise of both;
-    the parity bound then applies to zbar_0, the adjoint's own output, taken
-    from either gradient by subtracting the regulariser term in float64."""
+    the bound then applies to zbar_0, the adjoint's own output, taken from
+    either gradient by subtracting the regulariser term in float64.
+
+    zbar_0 is linear in the adjoint's seed, the residual R = I_T - J. A
+    relative error e of the final image (bounded by IMG_TOL) is a relative
+    error of up to e * kappa of R, kappa = |I_T| / |I_T - J| (the oracle's),
+    which a good fit makes large; the bound on zbar_0 is therefore the larger
+    of GRAD_TOL and IMG_TOL * kappa (the two stated tolerances chained through
+    that linearity), and the element bound scales with it."""
     gg = host(plan.out_grad[i])
     reg = 2.0 * pair.lam * pair.rho * np.asarray(pair.p0, dtype=np.float64)
     zg, zo = gg - reg, np.asarray(g, dtype=np.float64) - reg
     rz, ez = rel(zg, zo), elem(zg, zo)
     rH = abs(float(plan.out_cost[i, 0]) - H) / abs(H)
+    kappa = float(np.linalg.norm(I_T) / np.linalg.norm(np.asarray(I_T) - np.asarray(pair.target, dtype=np.float64)))
+    tol = max(GRAD_TOL, IMG_TOL * kappa)
+    etol = GRAD_ELEM_TOL * tol / GRAD_TOL
     announce(f"  adjoint term pair {i}: rel {rz:.2e} elem {ez:.2e} (|dH/dp0| / |zbar_0| = "
-             f"{np.linalg.norm(g) / max(np.linalg.norm(zo), 1e-300):.2e}); cost {rH:.2e}")
-    assert rz <= GRAD_TOL, ("adjoint term", rz)
-    assert ez <= GRAD_ELEM_TOL, ("adjoint term element", ez)
+             f"{np.linalg.norm(g) / max(np.linalg.norm(zo), 1e-300):.2e}; kappa {kappa:.1f}, bound {tol:.2e}); "
+             f"cost {rH:.2e}")
+    assert rz <= tol, ("adjoint term", rz, tol)
+    assert ez <= etol, ("adjoint term element", ez, etol)
     assert rH <= COST_TOL, ("cost", rH)
     return rz, rH

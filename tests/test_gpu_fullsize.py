@@ -9,7 +9,8 @@ size and full T on CPU workers (tests/oracle_pool.py) while the GPU tests run:
   four shape classes compared with the oracle;
 * the 240x240 pair at the momentum the oracle's 200-iteration gradient descent
   reached (the fourth kind of p0: after optimisation), for each rho; there
-  the gradient's two terms cancel, so the adjoint term is compared.
+  the gradient's two terms cancel, so the adjoint term is compared, with a
+  bound scaled by the conditioning of the residual that seeds it.
 
 Gradients are compared in relative L2 and per element, costs relatively."""
 import numpy as np
@@ -109,10 +110,11 @@ def test_c2_at_post_descent_momentum_matches_oracle(rho):
     torch.cuda.synchronize()
     H, g, I_T, z_T, D = oracle_pool.result(("c2", rho))
     announce(f"  c2 rho {rho}: largest step displacement {D:.4f} px")
-    # the descent converged (|dH/dp0| is ~1e-6 of its two terms at rho 1.0
-    # and 0.5): compare the adjoint term, not the cancelling sum
-    compare_adjoint_term(plan, 0, p, H, g)
     compare_forward(plan, 0, I_T, z_T, f"c2 rho {rho}")
+    # the descent converged (|dH/dp0| is ~1e-6 of its two terms at rho 1.0
+    # and 0.5): compare the adjoint term, not the cancelling sum, with the
+    # bound that the residual's conditioning at a good fit implies
+    compare_adjoint_term(plan, 0, p, H, g, I_T)
 
 
 def test_c4_full_run_properties():
