@@ -306,6 +306,26 @@ shoot_status shoot_plan_reset_stats(shoot_plan plan);
 shoot_status shoot_plan_kernel_stats(shoot_plan plan, int32_t index, const char** name, int64_t* launches,
                                      double* total_ms);
 
+/*
+ * Measurement reference: copies `bytes` (a multiple of 16) from src to dst
+ * (device pointers, 16-byte aligned, not overlapping: SHOOT_E_ARG otherwise)
+ * with a plain streaming kernel (one block of 256 threads per 16 KiB, each
+ * thread moving four 16-byte groups), asynchronously on `stream`. Its rate is
+ * the bandwidth a kernel that reads and writes every byte once can reach.
+ */
+shoot_status shoot_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/*
+ * Largest foot displacement max_a |dt v_a| of every pair and step recorded by
+ * the last execution call (its forward pass): out[i * T + t] for pair i and
+ * step t, host memory of n_pairs * T floats. The adjoint of a step takes the
+ * LDS gather when this is below 2 px (2-D) or 1 voxel (3-D), else the global
+ * atomic scatter. Synchronises `stream` (SHOOT_E_STATE under capture);
+ * SHOOT_E_ARG for SHOOT_UNFUSED plans. Values before the first execution call
+ * are unspecified.
+ */
+shoot_status shoot_plan_displacements(shoot_plan plan, float* out, void* stream);
+
 /* Release the plan's host memory, events and graphs (the shared streams
  * stay). NULL is a no-op. */
 shoot_status shoot_plan_destroy(shoot_plan plan);

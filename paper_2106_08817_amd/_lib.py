@@ -68,6 +68,8 @@ EXPORTS = {
     "shoot_lbfgs_step": (c_int32, [c_void_p, c_void_p]),
     "shoot_lbfgs_last_step": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(c_int32)]),
     "shoot_lbfgs_destroy": (c_int32, [c_void_p]),
+    "shoot_plan_displacements": (c_int32, [c_void_p, POINTER(c_float), c_void_p]),
+    "shoot_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "shoot_plan_set_profiling": (c_int32, [c_void_p, c_int32]),
     "shoot_plan_reset_stats": (c_int32, [c_void_p]),
     "shoot_plan_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_char_p), POINTER(ctypes.c_int64),

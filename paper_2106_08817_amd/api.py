@@ -16,6 +16,7 @@ from collections import OrderedDict
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -204,6 +205,15 @@ class Plan:
         arr = (ctypes.c_int32 * _lib.SHOOT_TUNE_COUNT)(*vals)
         _lib.check(self._lib.shoot_plan_set_tuning(self._plan, arr), "shoot_plan_set_tuning")
 
+    def displacements(self, stream=None) -> np.ndarray:
+        """[n_pairs, T] largest |dt v| of every pair and step of the last
+        execution call (synchronises the stream)."""
+        n = len(self.pairs)
+        out = np.zeros((n, self.T), dtype=np.float32)
+        _lib.check(self._lib.shoot_plan_displacements(self._plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                      _stream_ptr(stream)), "shoot_plan_displacements")
+        return out
+
     def set_profiling(self, enable: bool) -> None:
         """Eager launches with a HIP event pair around each kernel (diagnostics)."""
         _lib.check(self._lib.shoot_plan_set_profiling(self._plan, 1 if enable else 0), "shoot_plan_set_profiling")
@@ -354,3 +364,18 @@ def gradient_descent(pairs: Sequence[PairSpec], T: int, iters: int, eta: float =
         plan.descend(eta, reset=(it == 0))
         hist.append(plan.out_cost[:, 0].clone())
     return plan, torch.stack(hist) if hist else None
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst <- src through the library's streaming copy kernel (the bandwidth
+    reference of the measurements); contiguous device tensors of equal size,
+    a multiple of 16 bytes."""
+    if src.device.type != "cuda" or dst.device != src.device:
+        raise ValueError("src and dst must be on the same GPU")
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous")
+    nbytes = src.numel() * src.element_size()
+    if nbytes != dst.numel() * dst.element_size():
+        raise ValueError("src and dst sizes differ")
+    lib = _lib.load()
+    _lib.check(lib.shoot_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream_ptr(stream)), "shoot_stream_copy")

@@ -48,6 +48,8 @@ struct EpiArgs {
 };
 
 hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s);
+// dst <- src, n4 16-byte groups.
+hipError_t launch_stream_copy(const void* src, void* dst, long long n4, hipStream_t s);
 hipError_t launch_init(int ndim, const PairDev* pd, const Tile* tl, int nt, float* st, hipStream_t s);
 // cnt[pair] += number of non-finite values in the pair's image, target, p0.
 hipError_t launch_count_nonfinite(int ndim, const PairDev* pd, const Tile* tl, int nt, unsigned* cnt, hipStream_t s);

@@ -60,6 +60,23 @@ __global__ __launch_bounds__(NT) void k_fill_u32(unsigned* __restrict__ p, long 
     p[i] = v;
 }
 
+// Plain streaming copy of n4 16-byte groups (the achievable-bandwidth
+// reference of the measurements): block b moves groups [4 NT b, 4 NT (b + 1)),
+// each thread four of them NT apart, their loads in flight together.
+__global__ __launch_bounds__(NT) void k_stream_copy(const vf4* __restrict__ src, vf4* __restrict__ dst,
+                                                    long long n4) {
+  const long long i0 = (long long)blockIdx.x * (4 * NT) + threadIdx.x;
+  if (i0 + 3 * NT < n4) {
+    const vf4 a = src[i0], b = src[i0 + NT], c = src[i0 + 2 * NT], d = src[i0 + 3 * NT];
+    dst[i0] = a;
+    dst[i0 + NT] = b;
+    dst[i0 + 2 * NT] = c;
+    dst[i0 + 3 * NT] = d;
+  } else {
+    for (long long i = i0; i < n4; i += NT) dst[i] = src[i];
+  }
+}
+
 // State slot <- (S, p0) for every pair.
 template <int NDIM>
 __global__ __launch_bounds__(NT) void k_init(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
@@ -1589,6 +1606,14 @@ hipError_t launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t s) 
   if (n <= 0) return hipSuccess;
   const long long nb = (n + NT - 1) / NT;
   k_fill_u32<<<(unsigned)(nb < 4096 ? nb : 4096), NT, 0, s>>>(p, n, v);
+  return post();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, long long n4, hipStream_t s) {
+  if (n4 <= 0) return hipSuccess;
+  const long long nb = (n4 + 4 * NT - 1) / (4 * NT);
+  if (nb > 0x7fffffffll) return hipErrorInvalidValue;
+  k_stream_copy<<<(unsigned)nb, NT, 0, s>>>(reinterpret_cast<const vf4*>(src), reinterpret_cast<vf4*>(dst), n4);
   return post();
 }
 

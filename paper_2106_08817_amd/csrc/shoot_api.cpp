@@ -845,18 +845,30 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     g_err.clear();
     return SHOOT_OK;
   }
-  // admission: first-fit in order into groups whose field region fits the
+  // admission: first-fit in order into groups such that the whole workspace
+  // (every wave's header, then the largest group's field region) fits the
   // budget; each group is split into concurrent lanes
   const int want = (int)((flags & SHOOT_LANES_MASK) >> 8);
   const int lanes = want ? want : (p->ndim == 2 ? 3 : 2);
   std::vector<int> cur;
   std::vector<Wave> lw;
   size_t fb = 0;
+  size_t hdr_done = 0;  // header bytes of the committed groups' waves
+  auto headers = [&](std::vector<Wave>& ws) {
+    size_t h = 0;
+    for (Wave& w : ws) h = header_size(p, w, h);
+    return h;
+  };
   auto commit = [&]() {
     p->groups.emplace_back((int)p->waves.size(), (int)lw.size());
     p->lanes = std::max(p->lanes, (int)lw.size());
     p->field_max = std::max(p->field_max, fb);
+    hdr_done += headers(lw);
     for (Wave& w : lw) p->waves.push_back(w);
+  };
+  // workspace bytes if the group `ws` (field region `fbytes`) were committed next
+  auto total_with = [&](std::vector<Wave>& ws, size_t fbytes) {
+    return align_up(hdr_done + headers(ws), ALIGN) + std::max(p->field_max, fbytes);
   };
   if (!budget_bytes) {
     for (int i = 0; i < n_pairs; ++i) cur.push_back(i);
@@ -867,7 +879,7 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
       trial.push_back(i);
       std::vector<Wave> tw;
       const size_t tb = build_group(p, trial, lanes, tw);
-      if (!cur.empty() && tb > budget_bytes) {
+      if (!cur.empty() && total_with(tw, tb) > budget_bytes) {
         commit();
         cur.assign(1, i);
         fb = build_group(p, cur, lanes, lw);
@@ -876,10 +888,11 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
         lw = tw;
         fb = tb;
       }
-      if (cur.size() == 1 && fb > budget_bytes) {
+      if (cur.size() == 1 && total_with(lw, fb) > budget_bytes) {
         delete p;
-        return fail(SHOOT_E_BUDGET, "pair " + std::to_string(i) + " alone needs " + std::to_string(fb) +
-                                        " bytes, over the budget");
+        return fail(SHOOT_E_BUDGET, "pair " + std::to_string(i) + " alone needs " +
+                                        std::to_string(total_with(lw, fb)) + " bytes with the plan's headers, over "
+                                        "the budget");
       }
     }
   }
@@ -1044,6 +1057,38 @@ shoot_status shoot_descend(shoot_plan p, float eta0, int32_t reset, void* stream
   shoot_status st = execute(p, reset ? OP_DESCEND_RESET : OP_DESCEND, stream);
   if (st == SHOOT_OK) p->descend_ready = true;
   return st;
+}
+
+shoot_status shoot_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst) return fail(SHOOT_E_ARG, "NULL argument");
+  if (((uintptr_t)src | (uintptr_t)dst | bytes) % 16)
+    return fail(SHOOT_E_ARG, "pointers and size must be multiples of 16 bytes");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes && bytes) return fail(SHOOT_E_ARG, "src and dst overlap");
+  HIPCHK(launch_stream_copy(src, dst, (long long)(bytes / 16), (hipStream_t)stream));
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_displacements(shoot_plan p, float* out, void* stream) {
+  if (!p || !out) return fail(SHOOT_E_ARG, "NULL argument");
+  if (p->uf) return fail(SHOOT_E_ARG, "displacements are not recorded on the unfused path");
+  if (!p->ws) return fail(SHOOT_E_STATE, "plan is not bound to a workspace");
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s) HIPCHK(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(SHOOT_E_STATE, "reading displacements synchronises the stream");
+  for (Wave& w : p->waves) {
+    std::vector<unsigned> h(w.pdev.size() * (size_t)p->T);
+    HIPCHK(hipMemcpyAsync(h.data(), p->ws + w.o_dmax, h.size() * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t li = 0; li < w.ids.size(); ++li)
+      for (int t = 0; t < p->T; ++t) {
+        float v;
+        std::memcpy(&v, &h[li * p->T + t], sizeof(float));
+        out[(size_t)w.ids[li] * p->T + t] = v;
+      }
+  }
+  return SHOOT_OK;
 }
 
 shoot_status shoot_plan_set_profiling(shoot_plan p, int32_t enable) {

@@ -25,4 +25,7 @@ from .phantoms import (  # noqa: F401
     workload_pair,
     c5_shape_classes,
     small_pair,
+    large_step,
+    LARGE_STEP_T,
+    LARGE_STEP_SCALE,
 )

@@ -116,9 +116,48 @@ def test_budget_splits_into_waves():
     n2 = ctypes.c_size_t()
     lib.shoot_plan_workspace_bytes(h, ctypes.byref(n2))
     assert n2.value < n1.value
+    assert n2.value <= n1.value // 2  # the budget caps the whole workspace, headers included
     lib.shoot_plan_destroy(h)
     st, h = create(pairs, T=9, budget=1024)
     assert st == _lib.SHOOT_E_BUDGET
+
+
+@pytest.mark.parametrize("npairs,shape,T", [(64, (32, 32), 40), (6, (128, 128), 9), (9, (40, 52), 20)])
+def test_budget_caps_the_whole_workspace(npairs, shape, T):
+    """Every budget between one pair's need and the whole batch's: the
+    workspace (headers of every wave plus the largest field region) never
+    exceeds it, down to the last byte."""
+    lib = _lib.load()
+    pairs = [pair(shape=shape) for _ in range(npairs)]
+    st, h = create(pairs, T=T)
+    full = ctypes.c_size_t()
+    lib.shoot_plan_workspace_bytes(h, ctypes.byref(full))
+    lib.shoot_plan_destroy(h)
+    n = ctypes.c_size_t()
+    for budget in (full.value - 1, full.value * 3 // 4, full.value // 2, full.value // 5, full.value // 9):
+        st, h = create(pairs, T=T, budget=budget)
+        if st == _lib.SHOOT_E_BUDGET:
+            continue
+        assert st == _lib.SHOOT_OK
+        lib.shoot_plan_workspace_bytes(h, ctypes.byref(n))
+        assert n.value <= budget, (budget, n.value)
+        lib.shoot_plan_destroy(h)
+
+
+def test_displacements_and_stream_copy_validate_on_the_host():
+    lib = _lib.load()
+    st, h = create([pair()], T=4)
+    out = (ctypes.c_float * 4)()
+    assert lib.shoot_plan_displacements(h, out, None) == _lib.SHOOT_E_STATE  # not bound
+    assert lib.shoot_plan_displacements(h, None, None) == _lib.SHOOT_E_ARG
+    lib.shoot_plan_destroy(h)
+    st, h = create([pair()], T=4, flags=_lib.SHOOT_UNFUSED)
+    assert lib.shoot_plan_displacements(h, out, None) == _lib.SHOOT_E_ARG
+    lib.shoot_plan_destroy(h)
+    assert lib.shoot_stream_copy(None, FAKE, 64, None) == _lib.SHOOT_E_ARG
+    assert lib.shoot_stream_copy(FAKE, FAKE + 4096, 60, None) == _lib.SHOOT_E_ARG       # size not a multiple of 16
+    assert lib.shoot_stream_copy(FAKE + 4, FAKE + 4096, 64, None) == _lib.SHOOT_E_ARG   # misaligned
+    assert lib.shoot_stream_copy(FAKE, FAKE + 32, 64, None) == _lib.SHOOT_E_ARG         # overlapping
 
 
 def test_lanes_flag_and_count():
