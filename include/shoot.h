@@ -192,6 +192,28 @@ shoot_status shoot_plan_lanes(shoot_plan plan, int32_t* lanes);
 shoot_status shoot_plan_bind(shoot_plan plan, void* workspace, size_t bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): attaches
+ * the plan to the library's static scratch instead of a caller workspace and
+ * uploads its descriptors there, asynchronously on `stream`; execution calls
+ * then run as with shoot_plan_bind. Allocates nothing: the scratch is a
+ * file-scope device array of 64 MiB per GPU, held from the library's first use
+ * on that GPU until the process ends. SHOOT_E_WORKSPACE if the plan's
+ * workspace (shoot_plan_workspace_bytes) exceeds 64 MiB (e.g. a 240x240 pair
+ * at T = 20 needs about 10 MB, a 64^3 volume at T = 15 about 55 MB);
+ * SHOOT_E_ARG unless the plan was created with SHOOT_NO_GRAPH | SHOOT_LANES(1)
+ * (it runs eagerly on the caller's stream) or for SHOOT_UNFUSED plans.
+ * Every scratch-bound plan on a GPU shares that GPU's array, which keeps the
+ * last call's contents: an execution call of a plan other than the last one
+ * bound or run there uploads its descriptors again first (a shoot_descend
+ * without reset then fails with SHOOT_E_STATE, its step state being gone).
+ * Calls of scratch-bound plans that overlap on one GPU (other streams, other
+ * threads, or enqueued before the previous one completed on another stream)
+ * race for the array. shoot_plan_bind returns the plan to a caller workspace.
+ */
+shoot_status shoot_plan_bind_scratch(shoot_plan plan, void* stream);
+
+/*
  * Launch-shape tuning. A plan carries SHOOT_TUNE_COUNT choices, each 0 or 1
  * (0 = default), in this order:
  *   [0] x-pass rows per tile (at most one output group per thread / one

@@ -55,6 +55,7 @@ EXPORTS = {
     "shoot_plan_waves": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_plan_lanes": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_plan_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "shoot_plan_bind_scratch": (c_int32, [c_void_p, c_void_p]),
     "shoot_autotune": (c_int32, [c_void_p, c_void_p]),
     "shoot_plan_get_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_plan_set_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),

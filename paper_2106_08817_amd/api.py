@@ -72,7 +72,8 @@ class Plan:
 
     def __init__(self, pairs: Sequence[PairSpec], T: int, flags: int = 0, budget_bytes: int = 0,
                  stream: Optional[torch.cuda.Stream] = None, outputs: Sequence[str] = ("image", "momentum",
-                                                                                       "grad", "cost")):
+                                                                                       "grad", "cost"),
+                 scratch: bool = False):
         self._lib = _lib.load()
         self._plan = None
         if len(pairs) == 0:
@@ -129,12 +130,18 @@ class Plan:
             _lib.check(self._lib.shoot_plan_workspace_bytes(self._plan, ctypes.byref(nbytes)),
                        "shoot_plan_workspace_bytes")
             self.workspace_bytes = int(nbytes.value)
-            raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
-            shift = (-raw.data_ptr()) % 256
-            self._raw = raw
-            self.workspace = raw[shift:shift + self.workspace_bytes]
-            _lib.check(self._lib.shoot_plan_bind(self._plan, self.workspace.data_ptr(), self.workspace_bytes,
-                                                 _stream_ptr(stream)), "shoot_plan_bind")
+            if scratch:
+                # the library's static scratch: no workspace is allocated here
+                self._raw = self.workspace = None
+                _lib.check(self._lib.shoot_plan_bind_scratch(self._plan, _stream_ptr(stream)),
+                           "shoot_plan_bind_scratch")
+            else:
+                raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+                shift = (-raw.data_ptr()) % 256
+                self._raw = raw
+                self.workspace = raw[shift:shift + self.workspace_bytes]
+                _lib.check(self._lib.shoot_plan_bind(self._plan, self.workspace.data_ptr(), self.workspace_bytes,
+                                                     _stream_ptr(stream)), "shoot_plan_bind")
 
     @property
     def waves(self) -> int:

@@ -134,6 +134,7 @@ struct shoot_plan_s {
   std::vector<hipGraphExec_t> graph[OP_N];  // per wave
   float eta0 = 1.f;           // step of the descent after a reset
   bool descend_ready = false; // the descent's per-pair step state is initialised
+  bool scratch_bound = false; // bound to the library's static scratch (shoot_plan_bind_scratch)
   unfused::Plan* uf = nullptr;      // SHOOT_UNFUSED state
   bool profiling = false;
   Prof prof;
@@ -635,6 +636,51 @@ struct DevStreams {
 };
 std::mutex g_streams_mu;                 // guards g_streams
 std::mutex g_capture_mu;                 // one graph capture at a time on the shared capture stream
+
+// Static device scratch for plans bound without a caller workspace
+// (shoot_plan_bind_scratch): one array per device, held until the process
+// ends. Host code uses only the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in). The plan whose
+// header the array holds is its owner; an execution call of another
+// scratch-bound plan uploads that plan's header first.
+constexpr size_t SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+struct ScratchDev {
+  void* ptr = nullptr;
+  const shoot_plan_s* owner = nullptr;
+};
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;                         // guards g_scratch
+ScratchDev g_scratch[SCRATCH_DEVICES];           // [device]
+
+// The current device's scratch address (looked up once per device, with that
+// device current).
+hipError_t scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+  ScratchDev& d = g_scratch[dev];
+  if (!d.ptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr || ((uintptr_t)ptr) % ALIGN) return hipErrorInvalidSymbol;
+    d.ptr = ptr;
+  }
+  *out = d.ptr;
+  return hipSuccess;
+}
+
+// Before an execution call of a scratch-bound plan: upload its header if
+// another plan used the scratch since (the previous contents stay otherwise).
+shoot_status scratch_claim(shoot_plan_s* p, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  ScratchDev& d = g_scratch[p->device];
+  if (d.owner != p) {
+    if (p->header_total) HIPCHK(hipMemcpyAsync(p->ws, p->blob.data(), p->header_total, hipMemcpyHostToDevice, s));
+    d.owner = p;
+    p->descend_ready = false;
+  }
+  return SHOOT_OK;
+}
 std::vector<DevStreams> g_streams;       // [device]
 
 hipError_t device_streams(shoot_plan_s* p, int dev) {
@@ -714,6 +760,10 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
   HIPCHK(hipGetDevice(&dev));
   if (dev != p->device) return fail(SHOOT_E_STATE, "current device differs from the device the plan was bound on");
   hipStream_t s = (hipStream_t)stream;
+  if (p->scratch_bound) {
+    shoot_status st = scratch_claim(p, s);
+    if (st != SHOOT_OK) return st;
+  }
   if (p->uf) {
     hipError_t e = unfused::run(p->uf, op, s);
     if (e != hipSuccess) return fail(SHOOT_E_HIP, std::string("unfused path: ") + hipGetErrorString(e));
@@ -959,6 +1009,12 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
   p->device = dev;
   p->ws = (char*)workspace;
   p->descend_ready = false;
+  if (p->scratch_bound) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    for (ScratchDev& d : g_scratch)
+      if (d.owner == p) d.owner = nullptr;
+    p->scratch_bound = false;
+  }
   hipStream_t s = (hipStream_t)stream;
   if (p->uf) {
     hipError_t e = unfused::bind(p->uf, p->ws, s);
@@ -966,6 +1022,34 @@ shoot_status shoot_plan_bind(shoot_plan p, void* workspace, size_t bytes, void* 
     return SHOOT_OK;
   }
   if (p->header_total) HIPCHK(hipMemcpyAsync(p->ws, p->blob.data(), p->header_total, hipMemcpyHostToDevice, s));
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_bind_scratch(shoot_plan p, void* stream) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (p->uf) return fail(SHOOT_E_ARG, "the unfused path needs a caller workspace");
+  if (!(p->flags & SHOOT_NO_GRAPH) || p->lanes != 1)
+    return fail(SHOOT_E_ARG, "a scratch-bound plan runs eagerly in one lane: create it with SHOOT_NO_GRAPH | "
+                             "SHOOT_LANES(1)");
+  if (p->ws_bytes > SCRATCH_BYTES)
+    return fail(SHOOT_E_WORKSPACE, "plan needs " + std::to_string(p->ws_bytes) + " bytes of workspace; the static "
+                                   "scratch holds " + std::to_string(SCRATCH_BYTES) + " bytes");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  void* ptr = nullptr;
+  HIPCHK(scratch_ptr(dev, &ptr));
+  drop_graphs(p);
+  if (p->scratch_bound)
+    for (ScratchDev& d : g_scratch)
+      if (d.owner == p) d.owner = nullptr;
+  p->device = dev;
+  p->ws = (char*)ptr;
+  p->scratch_bound = true;
+  p->descend_ready = false;
+  if (p->header_total) HIPCHK(hipMemcpyAsync(p->ws, p->blob.data(), p->header_total, hipMemcpyHostToDevice, s));
+  g_scratch[dev].owner = p;
   return SHOOT_OK;
 }
 
@@ -1053,6 +1137,10 @@ shoot_status shoot_descend(shoot_plan p, float eta0, int32_t reset, void* stream
     p->eta0 = eta0;
   } else if (!p->descend_ready) {
     return fail(SHOOT_E_STATE, "the first shoot_descend call after a bind must reset");
+  } else if (p->scratch_bound) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[p->device].owner != p)
+      return fail(SHOOT_E_STATE, "another plan used the static scratch since the last call: the descent must reset");
   }
   shoot_status st = execute(p, reset ? OP_DESCEND_RESET : OP_DESCEND, stream);
   if (st == SHOOT_OK) p->descend_ready = true;
@@ -1116,6 +1204,11 @@ shoot_status shoot_plan_kernel_stats(shoot_plan p, int32_t index, const char** n
 
 shoot_status shoot_plan_destroy(shoot_plan p) {
   if (!p) return SHOOT_OK;
+  if (p->scratch_bound) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    for (ScratchDev& d : g_scratch)
+      if (d.owner == p) d.owner = nullptr;
+  }
   drop_graphs(p);
   p->prof.release();
   release_streams(p);
