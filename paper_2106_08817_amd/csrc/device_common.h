@@ -91,8 +91,11 @@ struct Axis {
 };
 
 __device__ __forceinline__ Axis foot_axis(int q, float d, int n) {
-  const float lo = (float)(-q), hi = (float)(n - 1 - q);
-  const float e = fminf(fmaxf(d, lo), hi);  // NaN d gives lo
+  const float qf = (float)q;
+  const float lo = -qf, hi = (float)(n - 1) - qf;
+  // clamp with one median-of-three; a NaN d gives lo
+  const float m = __builtin_amdgcn_fmed3f(d, lo, hi);
+  const float e = m == m ? m : lo;
   const float kf = floorf(e);
   const int yb = q + (int)kf;
   const bool top = yb > n - 2;              // only when the foot is on the last line
