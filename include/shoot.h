@@ -223,10 +223,13 @@ shoot_status shoot_plan_bind_scratch(shoot_plan plan, void* stream);
  *   [3] adjoint load batch (voxels per thread whose loads are in flight
  *       together: 2 / 4 in 2-D, 1 / 2 in 3-D)
  *   [4] adjoint epilogue: from an LDS-staged tile / by direct loads
+ *   [5] Gaussian pass along x on the vector units / on the fp32 matrix cores
+ *       (banded Toeplitz products, v_mfma_f32_16x16x4f32; for waves whose
+ *       every last extent is a multiple of 4, else the vector units)
  * Every choice computes each output with the same operations in the same
  * order, so results are bit-identical whatever is chosen.
  */
-#define SHOOT_TUNE_COUNT 5
+#define SHOOT_TUNE_COUNT 6
 
 /*
  * Pick the faster option of every tuning choice for this plan on the current

@@ -44,7 +44,7 @@ def SHOOT_LANES(n: int) -> int:
     """Plan flag fixing the number of concurrent lanes (1 <= n <= 8)."""
     return (int(n) & 15) << 8
 
-SHOOT_TUNE_COUNT = 5
+SHOOT_TUNE_COUNT = 6
 
 # Every function the header declares, with its ctypes signature.
 EXPORTS = {

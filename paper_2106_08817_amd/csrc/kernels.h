@@ -55,6 +55,10 @@ hipError_t launch_init(int ndim, const PairDev* pd, const Tile* tl, int nt, floa
 hipError_t launch_count_nonfinite(int ndim, const PairDev* pd, const Tile* tl, int nt, unsigned* cnt, hipStream_t s);
 hipError_t launch_xpass(int ndim, bool gradmul, const PairDev* pd, const Tile* tl, int nt, size_t lds,
                         const float* src, float* dst, hipStream_t s);
+// The x-pass on the matrix cores (kernels_mfma.hip); lds from xpass_mfma_lds.
+hipError_t launch_xpass_mfma(int ndim, bool gradmul, const PairDev* pd, const Tile* tl, int nt, size_t lds,
+                             const float* src, float* dst, hipStream_t s);
+size_t xpass_mfma_lds(int ndim, int nx, int r, int nrows);
 // rb: strided-pass outputs per thread (one of SPASS_RB); opt: tuning option
 // (0 or 1) selecting the load batch of the elementwise kernels.
 hipError_t launch_spass(int ndim, bool passz, int mode, int rb, const PairDev* pd, const Tile* tl, int nt,

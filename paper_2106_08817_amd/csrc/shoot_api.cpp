@@ -52,11 +52,13 @@ struct Wave {
   std::vector<PairDev> pdev;
   std::vector<Tile> tb;
   std::vector<Tile> ta;                   // 3-D adjoint tiles (ADJ3)
+  std::vector<Tile> tm;                   // x-pass tiles on the matrix cores (empty: not used)
+  size_t lds_m = 0;
   std::vector<Tile> tx[2], ty[2], tz[2];  // per tuning option of the x-pass / strided passes
   long long ntot = 0;                     // padded voxel total
   size_t lds_x[2] = {0, 0}, lds_y[2] = {0, 0}, lds_z[2] = {0, 0};
   // header offsets (bytes from the workspace base)
-  size_t o_pd = 0, o_tb = 0, o_ta = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
+  size_t o_pd = 0, o_tb = 0, o_ta = 0, o_tm = 0, o_tx[2] = {0, 0}, o_ty[2] = {0, 0}, o_tz[2] = {0, 0};
   size_t o_dmax = 0, o_rreg = 0, o_rssd = 0, o_eta = 0, o_prev = 0, o_nf = 0;
   size_t header_bytes = 0;
   size_t field_bytes = 0;
@@ -138,7 +140,7 @@ struct shoot_plan_s {
   unfused::Plan* uf = nullptr;      // SHOOT_UNFUSED state
   bool profiling = false;
   Prof prof;
-  int tune[TUNE_N] = {0, 0, 0, 0, 0};
+  int tune[TUNE_N] = {0, 0, 0, 0, 0, 0};
   bool has_def = false;        // some pair asks for its deformation map
 };
 
@@ -216,7 +218,16 @@ shoot_status validate(const shoot_pair* pairs, int32_t n, int32_t T) {
 
 // Builds descriptors and tile lists of one wave (header offsets are set later).
 void build_wave(shoot_plan_s* p, Wave& w) {
-  w.pdev.clear(); w.tb.clear(); w.ta.clear();
+  w.pdev.clear(); w.tb.clear(); w.ta.clear(); w.tm.clear();
+  w.lds_m = 0;
+  // the matrix-core x-pass needs every last extent a multiple of 4 and one
+  // staged row of every channel within the LDS limit
+  bool mfma = true;
+  for (int id : w.ids) {
+    const shoot_pair& q = p->pairs[id];
+    const int nx = q.shape[p->ndim - 1];
+    mfma = mfma && nx % 4 == 0 && xpass_mfma_lds(p->ndim, nx, radius_of(q.sigma), 1) <= LDS_HARD;
+  }
   for (int o = 0; o < 2; ++o) {
     w.tx[o].clear(); w.ty[o].clear(); w.tz[o].clear();
     w.lds_x[o] = w.lds_y[o] = w.lds_z[o] = 0;
@@ -278,6 +289,15 @@ void build_wave(shoot_plan_s* p, Wave& w) {
         w.lds_x[opt] = std::max(w.lds_x[opt], rb * (size_t)cnt);
       }
     }
+    if (mfma) {
+      int nr = XPASS_MFMA_ROWS[p->ndim - 2];
+      while (nr > 1 && xpass_mfma_lds(p->ndim, P.nx, P.r, nr) > LDS_HARD) --nr;
+      for (int r0 = 0; r0 < rows; r0 += nr) {
+        const int cnt = std::min(nr, rows - r0);
+        w.tm.push_back(Tile{pi, r0, cnt, 0});
+        w.lds_m = std::max(w.lds_m, xpass_mfma_lds(p->ndim, P.nx, P.r, cnt));
+      }
+    }
     // strided passes: tiles of 4 RB outputs along the pass axis
     for (int opt = 0; opt < 2; ++opt) {
       const int seg = (NT / 64) * SPASS_RB[opt];
@@ -330,6 +350,7 @@ size_t header_size(shoot_plan_s* p, Wave& w, size_t base) {
   w.o_pd = take(w.pdev.size() * sizeof(PairDev));
   w.o_tb = take(w.tb.size() * sizeof(Tile));
   w.o_ta = take(w.ta.size() * sizeof(Tile));
+  w.o_tm = take(w.tm.size() * sizeof(Tile));
   for (int o = 0; o < 2; ++o) {
     w.o_tx[o] = take(w.tx[o].size() * sizeof(Tile));
     w.o_ty[o] = take(w.ty[o].size() * sizeof(Tile));
@@ -358,8 +379,9 @@ struct Ctx {
   Wave* w;
   hipStream_t s;
   const PairDev* pd;
-  const Tile *tb, *ta, *tx, *ty, *tz;
-  int ntb, nta, ntx, nty, ntz;
+  const Tile *tb, *ta, *tm, *tx, *ty, *tz;
+  int ntb, nta, ntm, ntx, nty, ntz;
+  size_t lds_m;
   size_t lds_x, lds_y, lds_z;
   int rb;                 // strided-pass outputs per thread
   int o_adv, o_adj, o_epi;  // load-batch options
@@ -377,6 +399,7 @@ Ctx make_ctx(shoot_plan_s* p, Wave& w, hipStream_t s) {
   c.pd = (const PairDev*)(b + w.o_pd);
   c.tb = (const Tile*)(b + w.o_tb); c.ntb = (int)w.tb.size();
   c.ta = (const Tile*)(b + w.o_ta); c.nta = (int)w.ta.size();
+  c.tm = (const Tile*)(b + w.o_tm); c.ntm = p->tune[TUNE_XMFMA] ? (int)w.tm.size() : 0; c.lds_m = w.lds_m;
   const int ox = p->tune[TUNE_XPASS], os = p->tune[TUNE_SPASS];
   c.tx = (const Tile*)(b + w.o_tx[ox]); c.ntx = (int)w.tx[ox].size(); c.lds_x = w.lds_x[ox];
   c.ty = (const Tile*)(b + w.o_ty[os]); c.nty = (int)w.ty[os].size(); c.lds_y = w.lds_y[os];
@@ -425,7 +448,8 @@ float* AB(const Ctx& c, int t) { return c.ab + (size_t)(t & 1) * 2 * c.ntot; }
 // v_t = -G (z_t grad I_t) into the v slot of t.
 hipError_t velocity(const Ctx& c, int t) {
   const int nd = c.p->ndim;
-  LAUNCH(KI_XPASS_M, launch_xpass(nd, true, c.pd, c.tx, c.ntx, c.lds_x, ST(c, t), c.u, c.s));
+  if (c.ntm) LAUNCH(KI_XPASS_M, launch_xpass_mfma(nd, true, c.pd, c.tm, c.ntm, c.lds_m, ST(c, t), c.u, c.s));
+  else LAUNCH(KI_XPASS_M, launch_xpass(nd, true, c.pd, c.tx, c.ntx, c.lds_x, ST(c, t), c.u, c.s));
   if (nd == 2) {
     LAUNCH(KI_SPASS_V, launch_spass(2, false, 1, c.rb, c.pd, c.ty, c.nty, c.lds_y, c.u, VS(c, t), nullptr, c.s));
     return hipSuccess;
@@ -492,7 +516,8 @@ hipError_t bwd_step(const Ctx& c, int t) {
     LAUNCH(KI_ADV_ADJ, launch_adv_adj(nd, c.o_adj, c.ntb, a, c.s));
   }
   // mbar = -G vbar (+ -2 lambda v_0 at t = 0), written back into vb
-  LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.lds_x, c.vb, c.u, c.s));
+  if (c.ntm) LAUNCH(KI_XPASS_V, launch_xpass_mfma(nd, false, c.pd, c.tm, c.ntm, c.lds_m, c.vb, c.u, c.s));
+  else LAUNCH(KI_XPASS_V, launch_xpass(nd, false, c.pd, c.tx, c.ntx, c.lds_x, c.vb, c.u, c.s));
   const float* extra = t == 0 ? VS(c, 0) : nullptr;
   if (nd == 2) {
     LAUNCH(KI_SPASS_MBAR, launch_spass(2, false, 2, c.rb, c.pd, c.ty, c.nty, c.lds_y, c.u, c.vb, extra, c.s));
@@ -960,6 +985,7 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
     put(w.o_pd, w.pdev.data(), w.pdev.size() * sizeof(PairDev));
     put(w.o_tb, w.tb.data(), w.tb.size() * sizeof(Tile));
     put(w.o_ta, w.ta.data(), w.ta.size() * sizeof(Tile));
+    put(w.o_tm, w.tm.data(), w.tm.size() * sizeof(Tile));
     for (int o = 0; o < 2; ++o) {
       put(w.o_tx[o], w.tx[o].data(), w.tx[o].size() * sizeof(Tile));
       put(w.o_ty[o], w.ty[o].data(), w.ty[o].size() * sizeof(Tile));
@@ -1072,7 +1098,8 @@ shoot_status shoot_autotune(shoot_plan p, void* stream) {
       {KI_SPASS_MID, KI_SPASS_V, KI_SPASS_MBAR},
       {KI_ADVECT, -1, -1},
       {KI_ADV_ADJ, -1, -1},
-      {KI_EPILOGUE, -1, -1}};
+      {KI_EPILOGUE, -1, -1},
+      {KI_XPASS_M, KI_XPASS_V, -1}};
   const bool was_profiling = p->profiling;
   long long saved_n[KI_COUNT];
   double saved_ms[KI_COUNT];
@@ -1086,10 +1113,13 @@ shoot_status shoot_autotune(shoot_plan p, void* stream) {
       for (int k = 0; k < TUNE_N; ++k) p->tune[k] = saved_tune[k];
     drop_graphs(p);
   };
-  double t[TUNE_N][2] = {};
+  // pass 0: every choice 0; pass 1: every choice 1 but the matrix-core x-pass;
+  // pass 2: the matrix-core x-pass alone (it replaces the x-pass of both)
+  double t[3][TUNE_N] = {};
   p->profiling = true;
-  for (int opt = 0; opt < 2; ++opt) {
-    for (int k = 0; k < TUNE_N; ++k) p->tune[k] = opt;
+  for (int pass = 0; pass < 3; ++pass) {
+    for (int k = 0; k < TUNE_N; ++k) p->tune[k] = pass == 1 ? 1 : 0;
+    p->tune[TUNE_XMFMA] = pass == 2 ? 1 : 0;
     for (int rep = 0; rep < 4; ++rep) {  // the first evaluation warms up and is not counted
       for (int i = 0; i < KI_COUNT; ++i) { p->prof.launches[i] = 0; p->prof.ms[i] = 0.0; }
       shoot_status st = execute(p, op, stream);
@@ -1100,10 +1130,13 @@ shoot_status shoot_autotune(shoot_plan p, void* stream) {
       if (rep == 0) continue;
       for (int k = 0; k < TUNE_N; ++k)
         for (int j = 0; j < 3; ++j)
-          if (fam[k][j] >= 0) t[k][opt] += p->prof.ms[fam[k][j]];
+          if (fam[k][j] >= 0) t[pass][k] += p->prof.ms[fam[k][j]];
     }
   }
-  for (int k = 0; k < TUNE_N; ++k) p->tune[k] = (t[k][0] > 0.0 && t[k][1] < 0.97 * t[k][0]) ? 1 : 0;
+  for (int k = 0; k < TUNE_N; ++k)
+    if (k != TUNE_XMFMA) p->tune[k] = (t[0][k] > 0.0 && t[1][k] < 0.97 * t[0][k]) ? 1 : 0;
+  const double vec_x = p->tune[TUNE_XPASS] ? t[1][TUNE_XPASS] : t[0][TUNE_XPASS];
+  p->tune[TUNE_XMFMA] = (vec_x > 0.0 && t[2][TUNE_XMFMA] < 0.97 * vec_x) ? 1 : 0;
   restore(true);
   return SHOOT_OK;
 }

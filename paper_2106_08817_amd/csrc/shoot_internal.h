@@ -12,6 +12,10 @@ constexpr int RMAX = 31;
 // a multiple of 4 so the tap loops run in blocks of four.
 constexpr int WPAD = 4 * ((2 * RMAX + 1 + 3) / 4);   // 64
 
+// Rows per tile of the x-pass on the matrix cores (tuning choice TUNE_XMFMA;
+// all channels of the tile's rows are stacked 16 at a time).
+constexpr int XPASS_MFMA_ROWS[2] = {8, 16};  // [ndim - 2]
+
 // Threads per block for every kernel.
 constexpr int NT = 256;
 // Strided-pass tile: 64 columns along x x (NT/64) RB outputs along the pass
@@ -41,8 +45,9 @@ constexpr int EPI_BATCH[2] = {4, 2};  // [ndim - 2], epilogue without staging
 // tile (one output group per thread / the full fill batch), strided-pass
 // outputs per thread (SPASS_RB), advection from an LDS-staged tile or by
 // global gathers, the adjoint's load batch, and the epilogue from an
-// LDS-staged tile or direct loads.
-enum TuneKnob { TUNE_XPASS = 0, TUNE_SPASS, TUNE_ADVECT, TUNE_ADJ, TUNE_EPI, TUNE_N };
+// LDS-staged tile or direct loads, and the x-pass on the vector units or on
+// the fp32 matrix cores.
+enum TuneKnob { TUNE_XPASS = 0, TUNE_SPASS, TUNE_ADVECT, TUNE_ADJ, TUNE_EPI, TUNE_XMFMA, TUNE_N };
 // arrival points staged per adjoint tile: the tile grown by the bound on each side
 template <int NDIM>
 constexpr int ADJ_NQ() {

@@ -241,10 +241,13 @@ def test_tuning_choices_host_side():
     arr = (ctypes.c_int32 * _lib.SHOOT_TUNE_COUNT)()
     assert lib.shoot_plan_get_tuning(h, arr) == _lib.SHOOT_OK
     assert list(arr) == [0] * _lib.SHOOT_TUNE_COUNT            # defaults
-    want = [1, 0, 1, 1, 0]
-    assert lib.shoot_plan_set_tuning(h, (ctypes.c_int32 * 5)(*want)) == _lib.SHOOT_OK
+    n = _lib.SHOOT_TUNE_COUNT
+    want = [1, 0, 1, 1, 0, 1][:n]
+    assert lib.shoot_plan_set_tuning(h, (ctypes.c_int32 * n)(*want)) == _lib.SHOOT_OK
     assert lib.shoot_plan_get_tuning(h, arr) == _lib.SHOOT_OK and list(arr) == want
-    assert lib.shoot_plan_set_tuning(h, (ctypes.c_int32 * 5)(0, 2, 0, 0, 0)) == _lib.SHOOT_E_ARG
+    bad = [0] * n
+    bad[1] = 2
+    assert lib.shoot_plan_set_tuning(h, (ctypes.c_int32 * n)(*bad)) == _lib.SHOOT_E_ARG
     assert lib.shoot_plan_get_tuning(h, arr) == _lib.SHOOT_OK and list(arr) == want   # unchanged
     assert lib.shoot_plan_set_tuning(h, None) == _lib.SHOOT_E_ARG
     assert lib.shoot_plan_get_tuning(None, arr) == _lib.SHOOT_E_ARG

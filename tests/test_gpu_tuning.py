@@ -11,7 +11,7 @@ from paper_2106_08817_amd import Plan
 
 pytestmark = pytest.mark.gpu
 
-N_CHOICES = 5
+N_CHOICES = 6
 
 
 @pytest.fixture(autouse=True)
@@ -60,6 +60,31 @@ def test_every_tuning_option_is_bit_identical(ndim):
     plan.tuning = [1] * N_CHOICES
     plan.grad()
     assert_same(snapshot(plan), ref, "all options 1")
+
+
+def batch_x4(ndim):
+    """Every last extent a multiple of 4 (the matrix-core x-pass runs), with
+    ragged row tiles, a ragged 16-column tail and radii up to 30."""
+    if ndim == 2:
+        shapes, T, sig = [(37, 52), (21, 200), (30, 128)], 5, [2.0, 5.0, 10.0]
+    else:
+        shapes, T, sig = [(11, 13, 36), (7, 9, 20)], 4, [1.5, 3.0]
+    pairs = [G.small_pair(s, seed=740 + i, rho=0.5, sigma=sig[i], p0_kind="realistic", lam=0.01)
+             for i, s in enumerate(shapes)]
+    return pairs, T
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_matrix_core_xpass_is_bit_identical(ndim):
+    pairs, T = batch_x4(ndim)
+    plan = Plan(specs(pairs), T)
+    plan.grad()
+    ref = snapshot(plan)
+    for choice in ([0, 0, 0, 0, 0, 1], [1, 1, 1, 1, 1, 1]):
+        announce(f"ndim {ndim} tuning {choice}")
+        plan.tuning = choice
+        plan.grad()
+        assert_same(snapshot(plan), ref, f"choice {choice}")
 
 
 @pytest.mark.parametrize("ndim", [2, 3])
