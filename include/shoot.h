@@ -71,7 +71,8 @@ typedef enum shoot_status {
   SHOOT_E_WORKSPACE = -3, /* workspace missing, misaligned or too small */
   SHOOT_E_BUDGET = -4,    /* one pair alone exceeds the memory budget */
   SHOOT_E_HIP = -5,       /* a HIP runtime call failed (message has the HIP error) */
-  SHOOT_E_STATE = -6      /* call out of order (e.g. execute before bind) */
+  SHOOT_E_STATE = -6,     /* call out of order (e.g. execute before bind) */
+  SHOOT_E_IO = -7         /* a file could not be written (message names it) */
 } shoot_status;
 
 /*
@@ -242,6 +243,34 @@ shoot_status shoot_plan_bind_scratch(shoot_plan plan, void* stream);
  */
 shoot_status shoot_autotune(shoot_plan plan, void* stream);
 
+/*
+ * The plan's shape class, the part of a tuning-cache key that describes the
+ * plan: dimension, the operation the autotuner times (gradient or forward),
+ * log2 of the largest wave's voxel count, the range of ceil(log2) of the
+ * last extents, the largest Gaussian radius rounded up to a power of two,
+ * the lane count and the flags that change kernels (hexadecimal), e.g.
+ * "d3-grad-v25-x7_8-r16-l2-f0". Written NUL-terminated into buf (len bytes;
+ * SHOOT_E_ARG if it does not fit). Host-only.
+ */
+shoot_status shoot_plan_tune_class(shoot_plan plan, char* buf, size_t len);
+
+/*
+ * shoot_autotune with a persistent cache: the JSON file `path` maps
+ * "<gcnArchName>/<shape class>" (gcnArchName of the plan's device as HIP
+ * reports it) to the tuning choices,
+ *   {"format": "shoot-tune-1", "entries": {"<key>": [c0, c1, ...], ...}}.
+ * When the plan's key is present with SHOOT_TUNE_COUNT values, each 0 or 1,
+ * those choices are set and nothing runs (*hit = 1); otherwise the plan is
+ * autotuned as by shoot_autotune (its outputs written as by that call) and
+ * the file is rewritten with the new entry (*hit = 0); hit may be NULL. A
+ * missing or unreadable file counts as empty; one that is not in this format
+ * is replaced. The file is replaced whole (a temporary file renamed over
+ * it): of concurrent writers the last one's entries remain. SHOOT_E_IO when
+ * it cannot be written (the new choices are still set on the plan). A no-op
+ * for SHOOT_UNFUSED plans (*hit = 0).
+ */
+shoot_status shoot_autotune_cached(shoot_plan plan, const char* path, int32_t* hit, void* stream);
+
 /* Read / set the plan's tuning choices (arrays of SHOOT_TUNE_COUNT values;
  * each must be 0 or 1). Setting discards the plan's captured graphs. */
 shoot_status shoot_plan_get_tuning(shoot_plan plan, int32_t* choices);
@@ -264,6 +293,21 @@ shoot_status shoot_cost(shoot_plan plan, void* stream);
  * when given.
  */
 shoot_status shoot_grad_p0(shoot_plan plan, void* stream);
+
+/*
+ * Select the pairs that the execution calls (forward, cost, gradient,
+ * descent) work on: active[i] = 1 evaluates pair i, 0 skips it, so that its
+ * outputs (image, momentum, gradient, cost, deformation, descent step and p0)
+ * keep what the last call that evaluated it wrote, and its displacement
+ * record is stale; an optimiser whose pairs converge at different iterations
+ * evaluates only those still searching. `active` holds n_pairs values, each 0
+ * or 1 (SHOOT_E_ARG otherwise); NULL makes every pair active (the default).
+ * On a bound plan the selection is uploaded on `stream` (ordered before the
+ * calls enqueued after it there); not allowed while `stream` is being
+ * captured (SHOOT_E_STATE). Captured graphs stay valid: the kernels read the
+ * selection when they run. Not available on SHOOT_UNFUSED plans (SHOOT_E_ARG).
+ */
+shoot_status shoot_plan_set_active(shoot_plan plan, const int32_t* active, void* stream);
 
 /*
  * One fixed-step gradient-descent iteration on every pair (the optional
@@ -291,7 +335,9 @@ shoot_status shoot_descend(shoot_plan plan, float eta0, int32_t reset, void* str
  * steps t = 1, 1/2, ... for at most `trials` evaluations, accepting
  * H(x + t d) <= H(x) + c1 t g.d; a pair whose search fails stays at x and
  * forgets its history. Vector work runs on the device; every cost and
- * gradient comes from shoot_grad_p0 on the plan.
+ * gradient comes from shoot_grad_p0 on the plan, and after a step's first
+ * trial only the pairs still searching are evaluated (shoot_plan_set_active;
+ * every pair is active again when the step returns).
  *
  * The plan must be created with target, out_grad and out_cost for every pair
  * (SHOOT_E_ARG otherwise), stay bound and outlive the optimiser; p0 buffers

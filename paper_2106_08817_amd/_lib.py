@@ -19,6 +19,7 @@ SHOOT_E_WORKSPACE = -3
 SHOOT_E_BUDGET = -4
 SHOOT_E_HIP = -5
 SHOOT_E_STATE = -6
+SHOOT_E_IO = -7
 STATUS_NAMES = {
     SHOOT_OK: "SHOOT_OK",
     SHOOT_E_ARG: "SHOOT_E_ARG",
@@ -27,6 +28,7 @@ STATUS_NAMES = {
     SHOOT_E_BUDGET: "SHOOT_E_BUDGET",
     SHOOT_E_HIP: "SHOOT_E_HIP",
     SHOOT_E_STATE: "SHOOT_E_STATE",
+    SHOOT_E_IO: "SHOOT_E_IO",
 }
 
 SHOOT_FULL_STORE = 1
@@ -59,6 +61,9 @@ EXPORTS = {
     "shoot_autotune": (c_int32, [c_void_p, c_void_p]),
     "shoot_plan_get_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
     "shoot_plan_set_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "shoot_plan_set_active": (c_int32, [c_void_p, POINTER(c_int32), c_void_p]),
+    "shoot_plan_tune_class": (c_int32, [c_void_p, c_char_p, c_size_t]),
+    "shoot_autotune_cached": (c_int32, [c_void_p, c_char_p, POINTER(c_int32), c_void_p]),
     "shoot_forward": (c_int32, [c_void_p, c_void_p]),
     "shoot_cost": (c_int32, [c_void_p, c_void_p]),
     "shoot_grad_p0": (c_int32, [c_void_p, c_void_p]),

@@ -12,6 +12,7 @@ library's kernels.
 from __future__ import annotations
 
 import ctypes
+import os
 from collections import OrderedDict
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
@@ -197,6 +198,21 @@ class Plan:
         self._call(self._lib.shoot_autotune, "shoot_autotune", stream)
         return self.tuning
 
+    def autotune_cached(self, path, stream=None):
+        """Autotune through the JSON cache at ``path`` (keyed by the device's
+        gcnArchName and the plan's shape class); returns (tuning, hit)."""
+        hit = ctypes.c_int32(0)
+        _lib.check(self._lib.shoot_autotune_cached(self._plan, os.fsencode(path), ctypes.byref(hit),
+                                                   _stream_ptr(stream)), "shoot_autotune_cached")
+        return self.tuning, bool(hit.value)
+
+    @property
+    def tune_class(self) -> str:
+        """The plan's shape class (the plan's part of a tuning-cache key)."""
+        buf = ctypes.create_string_buffer(256)
+        _lib.check(self._lib.shoot_plan_tune_class(self._plan, buf, len(buf)), "shoot_plan_tune_class")
+        return buf.value.decode()
+
     @property
     def tuning(self) -> list:
         """The plan's launch-shape choices (SHOOT_TUNE_COUNT values, each 0 or 1)."""
@@ -211,6 +227,18 @@ class Plan:
             raise ValueError(f"expected {_lib.SHOOT_TUNE_COUNT} tuning choices, got {len(vals)}")
         arr = (ctypes.c_int32 * _lib.SHOOT_TUNE_COUNT)(*vals)
         _lib.check(self._lib.shoot_plan_set_tuning(self._plan, arr), "shoot_plan_set_tuning")
+
+    def set_active(self, active=None, stream=None) -> None:
+        """Evaluate only the pairs whose entry of ``active`` is true (None: all);
+        the others keep the outputs of the last call that evaluated them."""
+        if active is None:
+            arr = None
+        else:
+            vals = [1 if v else 0 for v in active]
+            if len(vals) != len(self.pairs):
+                raise ValueError(f"expected {len(self.pairs)} flags, got {len(vals)}")
+            arr = (ctypes.c_int32 * len(vals))(*vals)
+        _lib.check(self._lib.shoot_plan_set_active(self._plan, arr, _stream_ptr(stream)), "shoot_plan_set_active")
 
     def displacements(self, stream=None) -> np.ndarray:
         """[n_pairs, T] largest |dt v| of every pair and step of the last

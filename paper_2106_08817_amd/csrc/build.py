@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["kernels.hip", "kernels_adj3.hip", "kernels_mfma.hip", "kernels_unfused.hip", "kernels_opt.hip", "shoot_api.cpp", "lbfgs_api.cpp"]
+SOURCES = ["kernels.hip", "kernels_adj3.hip", "kernels_mfma.hip", "kernels_unfused.hip", "kernels_opt.hip", "shoot_api.cpp", "lbfgs_api.cpp", "tune_cache.cpp"]
 OUT = os.path.join(PKG, "libshoot.so")
 OBJ_DIR = os.path.join(ROOT, "_build")
 

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(NT) void k_init(const PairDev* __restrict__ pd, con
   using B = Blk<NDIM>;
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   float* __restrict__ I = st + 2 * P.off;
@@ -118,6 +119,7 @@ __global__ __launch_bounds__(NT) void k_count_nonfinite(const PairDev* __restric
   __shared__ unsigned bc;
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   if (threadIdx.x == 0) bc = 0u;
   __syncthreads();
@@ -157,6 +159,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   float* lds = reinterpret_cast<float*>(smem4);
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz, r = P.r, ntap4 = P.ntap4;
   const unsigned N = (unsigned)P.N;
   const int G4 = (nx + 3) >> 2;
@@ -353,6 +356,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   extern __shared__ vf4 smem4[];
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz, r = P.r, ntap4 = P.ntap4;
   const unsigned N = (unsigned)P.N;
   // pass axis: length ns, stride ss; third axis index t.b with stride so
@@ -521,6 +525,7 @@ __global__ __launch_bounds__(NT) void k_advect(const PairDev* __restrict__ pd, c
   const int tix = xcd_tile(gridDim.x);
   const Tile t = tl[tix];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   const unsigned sxy = (unsigned)(nx * ny);
@@ -766,6 +771,7 @@ __global__ __launch_bounds__(NT) void k_advect_lds(const PairDev* __restrict__ p
   const int tix = xcd_tile(gridDim.x);
   const Tile t = tl[tix];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   const unsigned sxy = (unsigned)(nx * ny);
@@ -1188,6 +1194,7 @@ __global__ __launch_bounds__(NT) void k_adv_adj_tile(const PairDev* __restrict__
   const Rec<NDIM> rec{rvec, rzb};
   const Tile tl = tla[xcd_tile(gridDim.x)];
   const PairDev& P = pd[tl.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   const float dt = P.dt, rdt = P.rho * P.dt;
@@ -1321,6 +1328,7 @@ __global__ __launch_bounds__(NT) void k_epilogue_lds(const PairDev* __restrict__
   __shared__ float sI[S::NS], sZ[S::NS], sMx[S::NVX], sMy[S::NVY], sMz[S::NVZ];
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   const float* __restrict__ MB = mbg + NDIM * P.off;
@@ -1403,6 +1411,7 @@ __global__ __launch_bounds__(NT) void k_epilogue(const PairDev* __restrict__ pd,
   static_assert(B::PPT % GS == 0, "batch must divide the voxels per thread");
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   const int sxy = nx * ny;
@@ -1483,6 +1492,7 @@ __global__ __launch_bounds__(NT) void k_finalize(const PairDev* __restrict__ pd,
                                                  const float* __restrict__ red_ssd) {
   __shared__ float sh[NT / 64];
   const PairDev& P = pd[blockIdx.x];
+  if (!P.active) return;
   float a = 0.f, b = 0.f;
   for (int i = threadIdx.x; i < P.elem_count; i += NT) {
     a += red_ssd ? red_ssd[P.elem_first + i] : 0.f;
@@ -1510,6 +1520,7 @@ __global__ __launch_bounds__(NT) void k_deform(const PairDev* __restrict__ pd, c
   constexpr int NC = NDIM == 3 ? 8 : 4;
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const unsigned N = (unsigned)P.N;
   const unsigned sxy = (unsigned)(nx * ny);
@@ -1565,7 +1576,7 @@ __global__ __launch_bounds__(NT) void k_descend_eta(const PairDev* __restrict__ 
                                                     float* __restrict__ eta, float* __restrict__ prev, int reset,
                                                     float eta0) {
   const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= npairs) return;
+  if (i >= npairs || !pd[i].active) return;
   const float H = pd[i].outCost[0];
   float e = reset ? eta0 : eta[i];
   if (!reset && H > prev[i]) e *= 0.5f;
@@ -1581,6 +1592,7 @@ __global__ __launch_bounds__(NT) void k_descend(const PairDev* __restrict__ pd, 
   using B = Blk<NDIM>;
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   float* __restrict__ p0 = const_cast<float*>(P.p0);
   const float* __restrict__ G = P.outG;
   const float e = eta[t.pair];

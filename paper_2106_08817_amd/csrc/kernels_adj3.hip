@@ -272,6 +272,7 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
   float* stage = reinterpret_cast<float*>(stage4);
   const Tile tl = tla[xcd_tile(gridDim.x)];
   const PairDev& P = pd[tl.pair];
+  if (!P.active) return;
   Adj3Ctx C;
   C.x0 = tl.a; C.y0 = tl.b; C.z0 = tl.c;
   C.nx = P.nx; C.ny = P.ny; C.nz = P.nz;

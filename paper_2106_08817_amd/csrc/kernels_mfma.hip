@@ -37,6 +37,7 @@ __global__ __launch_bounds__(NT) void k_xpass_mfma(const PairDev* __restrict__ p
   float* lds = reinterpret_cast<float*>(smem4);
   const Tile t = tl[xcd_tile(gridDim.x)];
   const PairDev& P = pd[t.pair];
+  if (!P.active) return;
   const int nx = P.nx, ny = P.ny, nz = P.nz, r = P.r;
   const unsigned N = (unsigned)P.N;
   const int row0 = t.a, nrows = t.b;

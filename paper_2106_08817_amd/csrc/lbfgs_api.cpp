@@ -16,7 +16,8 @@
 //   failure;
 // * d = -H g, replaced by -g / ||g|| when g.d >= 0;
 // * t = 1, 1/2, ... for at most `trials` evaluations, accepting
-//   H(x + t d) <= H(x) + c1 t g.d.
+//   H(x + t d) <= H(x) + c1 t g.d; a trial evaluates only the pairs still
+//   searching (shoot_plan_set_active).
 #include "shoot.h"
 
 #include <algorithm>
@@ -292,15 +293,37 @@ shoot_status shoot_lbfgs_step(shoot_lbfgs L, void* stream) {
     }
     if (any) LCHK(combine(D, G, ca, cb));
   }
-  // Armijo backtracking, every pair at once
+  // Armijo backtracking, every pair at once; after the first trial only the
+  // pairs still searching are evaluated (the others keep the cost and
+  // gradient of their accepted point)
   std::vector<double> t(n, 1.0), tfin(n, 0.0), fnew(L->f);
   std::vector<char> done(n, 0);
   int left = n;
+  std::vector<int32_t> searching(n, 1);
+  struct AllActive {  // every pair active again when the step ends, however it ends
+    shoot_plan plan;
+    void* stream;
+    bool set = false;
+    ~AllActive() {
+      if (set) (void)shoot_plan_set_active(plan, nullptr, stream);
+    }
+  } all_active{L->plan, stream};
+  auto select = [&]() -> shoot_status {
+    for (int i = 0; i < n; ++i) searching[i] = done[i] ? 0 : 1;
+    all_active.set = true;
+    shoot_status st = shoot_plan_set_active(L->plan, searching.data(), stream);
+    if (st != SHOOT_OK) return lfail(st, std::string("pair selection: ") + shoot_last_error());
+    return SHOOT_OK;
+  };
   for (int trial = 0; trial < L->trials && left > 0; ++trial) {
     std::vector<double> tt(n);
     for (int i = 0; i < n; ++i) tt[i] = done[i] ? tfin[i] : t[i];
     LCHK(upload(d.sc_a, tt, s));
     LCHK(set_p0(d.vp, d.vt, d.nt, X, D, d.sc_a, s));
+    if (left < n) {
+      shoot_status st = select();
+      if (st != SHOOT_OK) return st;
+    }
     shoot_status st = eval();
     if (st != SHOOT_OK) return st;
     for (int i = 0; i < n; ++i) {
@@ -313,12 +336,21 @@ shoot_status shoot_lbfgs_step(shoot_lbfgs L, void* stream) {
     }
   }
   if (left > 0) {
-    // failed pairs stay at x: evaluate once more so that every pair's
+    // failed pairs stay at x: evaluate them once more so that every pair's
     // gradient output is the gradient at its new point
     LCHK(upload(d.sc_a, tfin, s));
     LCHK(set_p0(d.vp, d.vt, d.nt, X, D, d.sc_a, s));
+    if (left < n) {
+      shoot_status st = select();
+      if (st != SHOOT_OK) return st;
+    }
     shoot_status st = eval();
     if (st != SHOOT_OK) return st;
+  }
+  if (all_active.set) {
+    all_active.set = false;
+    shoot_status st = shoot_plan_set_active(L->plan, nullptr, stream);
+    if (st != SHOOT_OK) return lfail(st, std::string("pair selection: ") + shoot_last_error());
   }
   // store (s, y) = (t d, g_new - g) in the ring; x, g <- new point
   const int k = L->head;

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -248,6 +249,7 @@ void build_wave(shoot_plan_s* p, Wave& w) {
     P.rho = q.rho;
     P.lam = q.lambda;
     P.dt = (float)(1.0 / (double)p->T);
+    P.active = 1;
     P.S = q.image; P.J = q.target; P.p0 = q.p0;
     P.outI = q.out_image; P.outZ = q.out_momentum; P.outG = q.out_grad; P.outCost = q.out_cost;
     P.outD = q.out_deformation;
@@ -854,6 +856,53 @@ shoot_status execute(shoot_plan_s* p, int op, void* stream) {
 
 }  // namespace
 
+namespace {
+
+// The operation the autotuner times: the gradient when every pair can take
+// it, else the forward shot.
+int autotune_op(const shoot_plan_s* p) {
+  int op = OP_GRAD;
+  for (const shoot_pair& q : p->pairs)
+    if (!q.target || !q.out_grad) op = OP_FORWARD;
+  if (p->flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED)) op = OP_FORWARD;
+  return op;
+}
+
+int ceil_log2(long long v) {
+  int k = 0;
+  while ((1LL << k) < v) ++k;
+  return k;
+}
+
+}  // namespace
+
+std::string shoot_internal_tune_class(shoot_plan p) {
+  if (!p) return "";
+  long long vmax = 0;
+  for (const Wave& w : p->waves) vmax = std::max(vmax, (long long)w.ntot);
+  int xlo = 1 << 30, xhi = 0, rmax = 0;
+  for (const shoot_pair& q : p->pairs) {
+    const int lx = ceil_log2(q.shape[q.ndim - 1]);
+    xlo = std::min(xlo, lx);
+    xhi = std::max(xhi, lx);
+    rmax = std::max(rmax, radius_of(q.sigma));
+  }
+  int rb = 1;
+  while (rb < rmax) rb *= 2;
+  int vlog = 0;
+  while ((2LL << vlog) <= vmax) ++vlog;
+  const uint32_t kf = p->flags & (SHOOT_FORCE_GLOBAL_SCATTER | SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED);
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "d%d-%s-v%d-x%d_%d-r%d-l%d-f%x", p->ndim, autotune_op(p) == OP_GRAD ? "grad" : "fwd",
+                vlog, xlo, xhi, rb, p->lanes, (unsigned)kf);
+  return buf;
+}
+
+int shoot_internal_device(shoot_plan p, int* unfused) {
+  if (unfused) *unfused = p && p->uf ? 1 : 0;
+  return p && (p->ws || p->uf) ? p->device : -1;
+}
+
 void shoot_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
 
 int shoot_internal_pairs(shoot_plan p, const shoot_pair** pairs, int* bound) {
@@ -1088,10 +1137,7 @@ shoot_status shoot_autotune(shoot_plan p, void* stream) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (s) HIPCHK(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return fail(SHOOT_E_STATE, "autotune cannot run under stream capture");
-  int op = OP_GRAD;
-  for (const shoot_pair& q : p->pairs)
-    if (!q.target || !q.out_grad) op = OP_FORWARD;
-  if (p->flags & (SHOOT_SCHEME_EULERIAN | SHOOT_SCHEME_MIXED)) op = OP_FORWARD;
+  const int op = autotune_op(p);
   // kernel families timed for each choice
   static const int fam[TUNE_N][3] = {
       {KI_XPASS_M, KI_XPASS_V, -1},
@@ -1141,6 +1187,14 @@ shoot_status shoot_autotune(shoot_plan p, void* stream) {
   return SHOOT_OK;
 }
 
+shoot_status shoot_plan_tune_class(shoot_plan p, char* buf, size_t len) {
+  if (!p || !buf) return fail(SHOOT_E_ARG, "NULL argument");
+  const std::string c = shoot_internal_tune_class(p);
+  if (c.size() + 1 > len) return fail(SHOOT_E_ARG, "buffer too small: need " + std::to_string(c.size() + 1) + " bytes");
+  std::memcpy(buf, c.c_str(), c.size() + 1);
+  return SHOOT_OK;
+}
+
 shoot_status shoot_plan_get_tuning(shoot_plan p, int32_t* choices) {
   if (!p || !choices) return fail(SHOOT_E_ARG, "NULL argument");
   for (int k = 0; k < TUNE_N; ++k) choices[k] = p->tune[k];
@@ -1154,6 +1208,40 @@ shoot_status shoot_plan_set_tuning(shoot_plan p, const int32_t* choices) {
       return fail(SHOOT_E_ARG, "tuning choice " + std::to_string(k) + " must be 0 or 1");
   for (int k = 0; k < TUNE_N; ++k) p->tune[k] = choices[k];
   drop_graphs(p);
+  return SHOOT_OK;
+}
+
+shoot_status shoot_plan_set_active(shoot_plan p, const int32_t* active, void* stream) {
+  if (!p) return fail(SHOOT_E_ARG, "plan is NULL");
+  if (p->uf) return fail(SHOOT_E_ARG, "pair selection is not available on the unfused path");
+  if (active)
+    for (int i = 0; i < p->npairs; ++i)
+      if (active[i] != 0 && active[i] != 1)
+        return fail(SHOOT_E_ARG, "active[" + std::to_string(i) + "] must be 0 or 1");
+  hipStream_t s = (hipStream_t)stream;
+  if (p->ws) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != p->device) return fail(SHOOT_E_STATE, "current device differs from the device the plan was bound on");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s) HIPCHK(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(SHOOT_E_STATE, "pair selection cannot run under stream capture");
+  }
+  for (Wave& w : p->waves)
+    for (size_t li = 0; li < w.ids.size(); ++li) {
+      const int32_t a = active ? active[w.ids[li]] : 1;
+      w.pdev[li].active = a;
+      std::memcpy(p->blob.data() + w.o_pd + li * sizeof(PairDev) + offsetof(PairDev, active), &a, sizeof(a));
+    }
+  if (!p->ws) return SHOOT_OK;  // the header goes up with the bind
+  if (p->scratch_bound) {
+    // the scratch holds another plan's header: this one is uploaded whole at its next call
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[p->device].owner != p) return SHOOT_OK;
+  }
+  for (Wave& w : p->waves)
+    HIPCHK(hipMemcpyAsync(p->ws + w.o_pd, p->blob.data() + w.o_pd, w.pdev.size() * sizeof(PairDev),
+                          hipMemcpyHostToDevice, s));
   return SHOOT_OK;
 }
 

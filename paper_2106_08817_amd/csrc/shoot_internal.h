@@ -67,7 +67,8 @@ struct alignas(16) PairDev {
   int elem_count; // number of block tiles of this pair
   long long off;  // voxel offset of the pair in the batch
   long long N;    // voxels
-  float rho, lam, dt, pad_;
+  float rho, lam, dt;
+  int active;     // 0: every kernel skips this pair (its outputs stay as they are)
   const float* S;
   const float* J;
   const float* p0;

@@ -256,6 +256,49 @@ def test_tuning_choices_host_side():
     lib.shoot_plan_destroy(h)
 
 
+def test_pair_selection_host_side():
+    lib = _lib.load()
+    st, h = create([pair(shape=(40, 36)), pair(shape=(20, 24)), pair(shape=(33, 17))], T=5)
+    assert st == _lib.SHOOT_OK
+    arr = lambda *v: (ctypes.c_int32 * len(v))(*v)  # noqa: E731
+    assert lib.shoot_plan_set_active(h, arr(1, 0, 1), None) == _lib.SHOOT_OK     # unbound: kept for the bind
+    assert lib.shoot_plan_set_active(h, arr(1, 2, 1), None) == _lib.SHOOT_E_ARG
+    assert lib.shoot_plan_set_active(h, arr(-1, 0, 1), None) == _lib.SHOOT_E_ARG
+    assert lib.shoot_plan_set_active(h, None, None) == _lib.SHOOT_OK             # all active
+    assert lib.shoot_plan_set_active(None, None, None) == _lib.SHOOT_E_ARG
+    lib.shoot_plan_destroy(h)
+    st, h = create([pair()], T=5, flags=_lib.SHOOT_UNFUSED)
+    assert st == _lib.SHOOT_OK
+    assert lib.shoot_plan_set_active(h, arr(1), None) == _lib.SHOOT_E_ARG          # not on the unfused path
+    lib.shoot_plan_destroy(h)
+
+
+def test_tune_class_and_cache_host_side():
+    lib = _lib.load()
+    # radii floor(3 sigma) = 6 and 9 -> 16; last extents 128 and 100 -> 2^7
+    st, h = create([pair(shape=(96, 128), sigma=2.0), pair(shape=(64, 100), sigma=3.0)], T=6)
+    assert st == _lib.SHOOT_OK
+    buf = ctypes.create_string_buffer(128)
+    assert lib.shoot_plan_tune_class(h, buf, len(buf)) == _lib.SHOOT_OK
+    cls = buf.value.decode()
+    m = re.fullmatch(r"d2-grad-v(\d+)-x7_7-r16-l(\d+)-f0", cls)
+    assert m, cls
+    # the largest wave holds one pair (lanes) or both: 2^13 <= 12288, 18688 < 2^15
+    assert int(m.group(1)) in (13, 14)
+    assert lib.shoot_plan_tune_class(h, buf, len(cls)) == _lib.SHOOT_E_ARG                # no room for the NUL
+    assert lib.shoot_plan_tune_class(h, buf, len(cls) + 1) == _lib.SHOOT_OK
+    hit = ctypes.c_int32(7)
+    assert lib.shoot_autotune_cached(h, b"/tmp/x.json", ctypes.byref(hit), None) == _lib.SHOOT_E_STATE
+    assert hit.value == 0
+    assert lib.shoot_autotune_cached(h, None, None, None) == _lib.SHOOT_E_ARG
+    lib.shoot_plan_destroy(h)
+    # forward-only plans (no target) are timed on the forward shot; 3-D
+    st, h = create([pair(ndim=3, shape=(20, 24, 36), sigma=1.0, target=None)], T=4)
+    assert st == _lib.SHOOT_OK
+    assert lib.shoot_plan_tune_class(h, buf, len(buf)) == _lib.SHOOT_OK
+    assert re.fullmatch(r"d3-fwd-v\d+-x6_6-r4-l\d+-f0", buf.value.decode()), buf.value
+
+
 def test_descend_requires_bind_and_validates_step():
     lib = _lib.load()
     st, h = create([pair(shape=(40, 52))], T=4)

@@ -48,3 +48,36 @@ def test_cost_and_grad_returns_the_batch_outputs():
         check_grad(plan, i, p, 4)
     with pytest.raises(ValueError):
         Plan(specs(pairs), 4, outputs=("image",)).cost_and_grad()
+
+
+def test_pair_selection_skips_inactive_pairs():
+    """Inactive pairs keep the outputs of their last evaluation; active ones
+    get exactly what a plan of all pairs gives."""
+    shapes = [(40, 52), (33, 29), (61, 47)]
+    pairs = [G.small_pair(s, 90 + i, rho=0.5, sigma=2.0, p0_kind="realistic") for i, s in enumerate(shapes)]
+    T = 5
+    sp = specs(pairs)
+    plan = Plan(sp, T)
+    plan.grad()
+    torch.cuda.synchronize()
+    old = [(host(plan.out_grad[i]).copy(), host(plan.out_cost[i]).copy()) for i in range(3)]
+    for spec in sp:   # new momenta for every pair
+        spec.p0.mul_(0.5)
+    plan.set_active([True, False, True])
+    plan.grad()
+    torch.cuda.synchronize()
+    ref = Plan(specs(pairs), T)   # the same pairs (halved p0 from the shared buffers)
+    for i, spec in enumerate(sp):
+        ref.pairs[i].p0.copy_(spec.p0)
+    ref.grad()
+    torch.cuda.synchronize()
+    for i in (0, 2):
+        assert np.array_equal(host(plan.out_grad[i]), host(ref.out_grad[i]))
+        assert np.array_equal(host(plan.out_cost[i]), host(ref.out_cost[i]))
+    assert np.array_equal(host(plan.out_grad[1]), old[1][0])
+    assert np.array_equal(host(plan.out_cost[1]), old[1][1])
+    plan.set_active(None)
+    plan.grad()
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert np.array_equal(host(plan.out_grad[i]), host(ref.out_grad[i]))

@@ -1,13 +1,16 @@
 """Launch-shape tuning: every option of every choice gives bit-identical
 outputs (each output is computed by the same operations in the same order),
 and the autotuner leaves a valid choice that reproduces the default run."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import synthetic as G
 from gpu_util import announce, host, specs
-from paper_2106_08817_amd import Plan
+from paper_2106_08817_amd import Plan, _lib
 
 pytestmark = pytest.mark.gpu
 
@@ -98,3 +101,43 @@ def test_autotune_picks_valid_choices_and_keeps_results(ndim):
     assert_same(snapshot(plan), ref, "outputs written by autotune")
     plan.grad()
     assert_same(snapshot(plan), ref, f"after autotune {chosen}")
+
+
+def test_autotune_cache_miss_hit_and_replacement(tmp_path):
+    pairs, T = batch(2)
+    path = str(tmp_path / "tune.json")
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    plan = Plan(specs(pairs), T)
+    plan.grad()
+    ref = snapshot(plan)
+    chosen, hit = plan.autotune_cached(path)
+    assert not hit and len(chosen) == N_CHOICES
+    assert_same(snapshot(plan), ref, "outputs written by the cached autotune")
+    doc = json.load(open(path))
+    key = f"{arch}/{plan.tune_class}"
+    assert doc == {"format": "shoot-tune-1", "entries": {key: chosen}}
+    # a second plan of the same class takes the stored choices without timing
+    other = Plan(specs(pairs), T)
+    assert other.tune_class == plan.tune_class
+    stored = [1 - c for c in chosen]            # a planted entry proves the read
+    json.dump({"format": "shoot-tune-1", "entries": {key: stored, "gfx0/other": [0] * N_CHOICES}}, open(path, "w"))
+    got, hit = other.autotune_cached(path)
+    assert hit and got == stored and other.tuning == stored
+    other.grad()
+    assert_same(snapshot(other), ref, "after a cache hit")
+    # wrong length or values: a miss, and the entry is replaced; other keys stay
+    json.dump({"format": "shoot-tune-1", "entries": {key: [2] * N_CHOICES, "gfx0/other": [1] * N_CHOICES}},
+              open(path, "w"))
+    got, hit = other.autotune_cached(path)
+    assert not hit
+    doc = json.load(open(path))
+    assert doc["entries"] == {key: got, "gfx0/other": [1] * N_CHOICES}
+    # not the format: replaced
+    open(path, "w").write("not json")
+    got, hit = other.autotune_cached(path)
+    assert not hit and json.load(open(path)) == {"format": "shoot-tune-1", "entries": {key: got}}
+    # cannot write: SHOOT_E_IO, the choices still set
+    bad = str(tmp_path / "missing_dir" / "tune.json")
+    with pytest.raises(_lib.ShootError, match="SHOOT_E_IO"):
+        other.autotune_cached(bad)
+    assert not os.path.exists(bad)
