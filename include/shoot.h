@@ -139,7 +139,8 @@ typedef struct shoot_plan_s* shoot_plan;
  * identical whatever the lane count: pairs are independent and every pair's
  * arithmetic is the same. SHOOT_LANES(n), 1 <= n <= SHOOT_MAX_LANES, fixes the
  * count; without it a plan takes 3 lanes in 2-D and 2 in 3-D (at most one
- * lane per pair). The last lane runs on the caller's stream, the others on a
+ * lane per pair), and one lane for a wave of at least 2^23 voxels, whose
+ * launches fill the GPU by themselves. The last lane runs on the caller's stream, the others on a
  * pool of streams that the library creates at the first bind on a device (3
  * lane streams, more when a plan asks for more lanes, then one graph-capture
  * stream), shared by all plans and kept until the process ends; lanes gain

@@ -176,6 +176,20 @@ def test_lanes_flag_and_count():
     lib.shoot_plan_lanes(h, ctypes.byref(n))
     assert n.value == 2
     lib.shoot_plan_destroy(h)
+    # a wave of at least 2^23 voxels runs as one lane unless the count is fixed
+    big = [pair(ndim=3, shape=(128, 128, 256)) for _ in range(2)]      # 2 x 2^22 voxels
+    st, h = create(big, T=4)
+    lib.shoot_plan_lanes(h, ctypes.byref(n))
+    assert st == _lib.SHOOT_OK and n.value == 1
+    lib.shoot_plan_destroy(h)
+    st, h = create(big[:1] + [pair(ndim=3, shape=(128, 128, 252))], T=4)   # just below
+    lib.shoot_plan_lanes(h, ctypes.byref(n))
+    assert st == _lib.SHOOT_OK and n.value == 2
+    lib.shoot_plan_destroy(h)
+    st, h = create(big, T=4, flags=_lib.SHOOT_LANES(2))
+    lib.shoot_plan_lanes(h, ctypes.byref(n))
+    assert st == _lib.SHOOT_OK and n.value == 2
+    lib.shoot_plan_destroy(h)
     # fixed counts; the workspace hardly depends on them (lane alignment only)
     sizes = {}
     for k in (1, 2, 6):
