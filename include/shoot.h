@@ -222,8 +222,8 @@ shoot_status shoot_plan_bind_scratch(shoot_plan plan, void* stream);
  *       full fill batch)
  *   [1] strided (y/z) pass outputs per thread (16 / 8)
  *   [2] advection: from an LDS-staged tile / by global gathers
- *   [3] adjoint load batch (voxels per thread whose loads are in flight
- *       together: 2 / 4 in 2-D, 1 / 2 in 3-D)
+ *   [3] adjoint load batch in 2-D (voxels per thread whose loads are in
+ *       flight together: 2 / 4; the 3-D adjoint has one form)
  *   [4] adjoint epilogue: from an LDS-staged tile / by direct loads
  *   [5] Gaussian pass along x on the vector units / on the fp32 matrix cores
  *       (banded Toeplitz products, v_mfma_f32_16x16x4f32; for waves whose

@@ -1699,14 +1699,11 @@ hipError_t launch_advect(int ndim, int opt, int nt, const AdvectArgs& a, hipStre
   return post();
 }
 
+// 2-D only: the 3-D adjoint is k_adv_adj3 (launch_adv_adj3).
 hipError_t launch_adv_adj(int ndim, int opt, int nt, const AdjArgs& a, hipStream_t s) {
-  if (ndim == 2) {
-    if (opt == 0) k_adv_adj_tile<2, ADJ_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
-    else k_adv_adj_tile<2, ADJ_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
-  } else {
-    if (opt == 0) k_adv_adj_tile<3, ADJ_BATCH[1][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
-    else k_adv_adj_tile<3, ADJ_BATCH[1][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
-  }
+  if (ndim != 2) return hipErrorInvalidValue;
+  if (opt == 0) k_adv_adj_tile<2, ADJ_BATCH[0][0]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
+  else k_adv_adj_tile<2, ADJ_BATCH[0][1]><<<nt, NT, 0, s>>>(a.pd, a.tl, a.V, a.st, a.ab_in, a.sc, a.vb, a);
   return post();
 }
 

@@ -38,7 +38,7 @@ constexpr int ADJ3_X = 16, ADJ3_Y = 8, ADJ3_Z = 8;
 // flight together; larger batches trade registers, hence occupancy, for
 // memory-level parallelism per wave), per tuning option: [ndim - 2][option].
 constexpr int ADV_BATCH[2] = {2, 1};  // [ndim - 2], global-gather advection
-constexpr int ADJ_BATCH[2][2] = {{2, 4}, {1, 2}};
+constexpr int ADJ_BATCH[1][2] = {{2, 4}};  // 2-D block-tile adjoint only
 constexpr int ADJ_RING_BATCH2 = 2, ADJ_RING_BATCH3 = 1;
 constexpr int EPI_BATCH[2] = {4, 2};  // [ndim - 2], epilogue without staging
 // Tuning choices of a plan (each 0 or 1; 0 is the default): x-pass rows per
