@@ -81,3 +81,29 @@ def test_pair_selection_skips_inactive_pairs():
     torch.cuda.synchronize()
     for i in range(3):
         assert np.array_equal(host(plan.out_grad[i]), host(ref.out_grad[i]))
+
+
+def test_pair_selection_3d_and_descent():
+    """3-D pairs in two lanes: an inactive pair's gradient, cost and p0 stay
+    as they were through gradient and descent calls; the active ones match a
+    plan of them alone, step for step."""
+    shapes = [(10, 12, 16), (9, 14, 11), (12, 10, 13)]
+    pairs = [G.small_pair(s, 120 + i, rho=0.4, sigma=1.5, p0_kind="realistic") for i, s in enumerate(shapes)]
+    T = 4
+    sp = specs(pairs)
+    plan = Plan(sp, T)
+    plan.grad()
+    torch.cuda.synchronize()
+    g1, c1, p1 = host(plan.out_grad[1]).copy(), host(plan.out_cost[1]).copy(), host(sp[1].p0).copy()
+    plan.set_active([True, False, True])
+    alone = Plan(specs([pairs[0], pairs[2]]), T)
+    for it in range(3):
+        plan.descend(0.5, reset=(it == 0))
+        alone.descend(0.5, reset=(it == 0))
+    torch.cuda.synchronize()
+    for i, j in ((0, 0), (2, 1)):
+        assert np.array_equal(host(plan.out_grad[i]), host(alone.out_grad[j]))
+        assert np.array_equal(host(sp[i].p0), host(alone.pairs[j].p0))
+    assert np.array_equal(host(plan.out_grad[1]), g1)
+    assert np.array_equal(host(plan.out_cost[1]), c1)
+    assert np.array_equal(host(sp[1].p0), p1)
