@@ -123,7 +123,7 @@ typedef struct shoot_plan_s* shoot_plan;
 #define SHOOT_FULL_STORE 1u            /* keep all T states instead of sqrt(T) checkpoints */
 #define SHOOT_UNFUSED 2u               /* per-pair, one kernel per primitive (baseline) */
 #define SHOOT_NO_GRAPH 4u              /* launch kernels eagerly, no internal HIP graph */
-#define SHOOT_FORCE_GLOBAL_SCATTER 8u  /* adjoint scatter through global atomics only */
+#define SHOOT_FORCE_GLOBAL_SCATTER 8u  /* adjoint scatter through per-corner global atomics only */
 /* Integration options the paper compares with the full semi-Lagrangian scheme
  * (semi-Lagrangian section; forward and cost only, SHOOT_E_ARG for the
  * gradient): Eulerian: explicit Euler with clamped central differences,
@@ -391,8 +391,8 @@ shoot_status shoot_stream_copy(const void* src, void* dst, size_t bytes, void* s
  * Largest foot displacement max_a |dt v_a| of every pair and step recorded by
  * the last execution call (its forward pass): out[i * T + t] for pair i and
  * step t, host memory of n_pairs * T floats. The adjoint of a step takes the
- * LDS gather when this is below 2 px (2-D) or 1 voxel (3-D), else the global
- * atomic scatter. Synchronises `stream` (SHOOT_E_STATE under capture);
+ * LDS gather when this is below 2 px (2-D) or 1 voxel (3-D), in 3-D the
+ * scatter into an LDS box below 2 voxels, else the global atomic scatter. Synchronises `stream` (SHOOT_E_STATE under capture);
  * SHOOT_E_ARG for SHOOT_UNFUSED plans. Values before the first execution call
  * are unspecified.
  */

@@ -30,11 +30,15 @@
 // reaches, in a fixed order, without atomics: deterministic, each output
 // written once.
 //
-// When D >= 1 voxel (or a forced global scatter) the block instead scatters
-// its own arrival points with global float atomics into the accumulator that
-// the previous adjoint step (or the last forward step) cleared; the foot
-// corners are then read from global memory. Velocity and divergence still
-// come from LDS.
+// When 1 <= D < 2 voxels every corner of an own point's foot lies in P +- 2:
+// the block adds its own points' Interp^T with LDS atomics into a box over
+// P +- 2 (in the records' space) and then adds each touched cell of the box
+// with one global float atomic into the accumulator that the previous adjoint
+// step (or the last forward step) cleared, about a third of the global
+// atomics of a per-corner scatter. When D >= 2 (or a forced global scatter)
+// the own points scatter per corner with global float atomics. In both the
+// ring points' foot corners come from global memory; velocity and divergence
+// still come from LDS. Sums through atomics depend on their order.
 #include "kernels.h"
 #include "device_common.h"
 
@@ -78,6 +82,9 @@ constexpr int RX = AX + 2, RY = AY + 2, RZ = AZ + 2;
 constexpr int RXP = AX + 3;
 constexpr int NRP = RXP * RY * RZ;
 constexpr int NOWN = AX * AY * AZ;
+// LDS scatter box over P +- 2 (1 <= D < 2): rows of LXW floats
+constexpr int LXW = AX + 4, LPL = LXW * (AY + 4), LBOX = LPL * (AZ + 4);
+__device__ __forceinline__ int lidx(int cx, int cy, int cz) { return ((cz + 2) * (AY + 4) + cy + 2) * LXW + cx + 2; }
 constexpr int NRING = RX * RY * RZ - NOWN;
 constexpr int RING_B = (NRING + NT - 1) / NT;  // ring points per thread (rounds)
 // the own points' foot-point parts of vbar, handed from phase 1 to phase 2
@@ -88,6 +95,7 @@ static_assert(SXW % 4 == 0 && SPL % 4 == 0 && BOXP % 4 == 0, "16-byte groups");
 static_assert(O_VQ % 4 == 0 && VQR % 4 == 0 && VQP % 4 == 0, "16-byte vbar rows");
 static_assert(O_VQ + 3 * VQN <= NF * BOXP, "records and vbar parts fit in the staged fields' space");
 static_assert(FILL_U % 2 == 0, "fill rounds in pairs");
+static_assert(2 * LBOX % 4 == 0 && 2 * LBOX <= O_VQ, "the LDS scatter box fits below the vbar parts");
 
 constexpr int SBY = SXW, SBZ = SPL;
 __device__ __forceinline__ int bidx(int lx, int ly, int lz) { return (lz + 2) * SPL + (ly + 2) * SXW + lx + 4; }
@@ -188,14 +196,30 @@ struct Adj3Ctx {
   float* dbar;                   // div_bar on P +- 1 (LDS)
 };
 
+// How a block forms Interp^T (chosen per pair and step from D = max |dt v|):
+// a gather over the records in LDS (D < 1), atomics into an LDS box over
+// P +- 2 flushed with one global atomic per cell (1 <= D < 2), or global
+// atomics per corner (D >= 2, or a forced global scatter).
+constexpr int M_GATHER = 0, M_LDS = 1, M_GLOBAL = 2;
+
+// A foot's cell (relative to the tile origin), fractions and cotangents, for
+// the LDS scatter.
+struct Scat {
+  int cx, cy, cz;
+  float fx, fy, fz, ib, zhb;
+};
+
 // Phase 1 at one arrival point, local coordinates (lx, ly, lz) in P +- 1.
 // The point's computations use its coordinates clamped into the image; act
-// marks a point inside the image (only those contribute). STAGED: the foot
-// corners come from LDS (D < 1); otherwise from global memory, and own points
-// scatter Interp^T with global atomics.
-template <bool OWN, bool STAGED>
+// marks a point inside the image (only those contribute). The foot corners
+// come from LDS in M_GATHER, and for own points in M_LDS (|e| < 2 keeps them
+// within P +- 2); otherwise from global memory. M_GATHER keeps the record,
+// M_LDS the foot's cell and weights, M_GLOBAL scatters an own point's
+// Interp^T with global atomics.
+template <bool OWN, int MODE>
 __device__ __forceinline__ void adj3_point(const Adj3Ctx& C, int lx, int ly, int lz, bool act, float ib, float zb,
-                                           Rec5& rec, float vq[3]) {
+                                           Rec5& rec, Scat& sc, float vq[3]) {
+  constexpr bool STAGED = MODE == M_GATHER || (MODE == M_LDS && OWN);
   const int qx = clampi3(C.x0 + lx, C.nx), qy = clampi3(C.y0 + ly, C.ny), qz = clampi3(C.z0 + lz, C.nz);
   const int b = bidx(qx - C.x0, qy - C.y0, qz - C.z0);
   const float* S = C.st;
@@ -239,14 +263,19 @@ __device__ __forceinline__ void adj3_point(const Adj3Ctx& C, int lx, int ly, int
     zh = trilin(zc, az.f, ay.f, ax.f);
   }
   if (act) C.dbar[ridx(lx, ly, lz)] = -C.dt * zh * zb;
-  if (STAGED) {
+  if (MODE == M_GATHER) {
     // cotangents scaled by 1/8 for the scaled hats of the gather
     rec.ex = act ? ax.e : 0.f;
     rec.ey = act ? ay.e : 0.f;
     rec.ez = act ? az.e : 0.f;
     rec.ib = act ? 0.125f * ib : 0.f;
     rec.zhb = act ? 0.125f * zhb : 0.f;
-  } else if (OWN && act) {
+  } else if (MODE == M_LDS && OWN) {
+    sc.cx = ax.i - C.x0; sc.cy = ay.i - C.y0; sc.cz = az.i - C.z0;
+    sc.fx = ax.f; sc.fy = ay.f; sc.fz = az.f;
+    sc.ib = act ? ib : 0.f;
+    sc.zhb = act ? zhb : 0.f;
+  } else if (MODE == M_GLOBAL && OWN && act) {
     const float wz[2] = {1.f - az.f, az.f}, wy[2] = {1.f - ay.f, ay.f}, wx[2] = {1.f - ax.f, ax.f};
     const unsigned sxy = (unsigned)(C.nx * C.ny);
     const unsigned c0 = (unsigned)((az.i * C.ny + ay.i) * C.nx + ax.i);
@@ -291,6 +320,7 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
   const unsigned N = C.N;
   const float D = __uint_as_float(A.dmax[(long long)tl.pair * A.T + A.t]);
   const bool gmode = !A.force_global && D < 1.f;
+  const bool lmode = !A.force_global && !gmode && D < 2.f;
   const bool vec = (nx & 3) == 0;
 
   const int gx = threadIdx.x & 3, oly = (threadIdx.x >> 2) & (AY - 1), olz = threadIdx.x >> 5;
@@ -373,12 +403,14 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
 
   // phase 1: own points and the ring
   Rec5 orec[4], rrec[RING_B];
+  Scat osc[4], dsc;
   float vq[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const bool act = orow && C.x0 + gx + 4 * k < nx;
-    if (gmode) adj3_point<true, true>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], vq[k]);
-    else adj3_point<true, false>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], vq[k]);
+    if (gmode) adj3_point<true, M_GATHER>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    else if (lmode) adj3_point<true, M_LDS>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    else adj3_point<true, M_GLOBAL>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
   }
 #pragma unroll
   for (int u = 0; u < RING_B; ++u) {
@@ -387,8 +419,8 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
       const int qx = C.x0 + lx, qy = C.y0 + ly, qz = C.z0 + lz;
       const bool act = qx >= 0 && qx < nx && qy >= 0 && qy < ny && qz >= 0 && qz < nz;
       float dummy[3];
-      if (gmode) adj3_point<false, true>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dummy);
-      else adj3_point<false, false>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dummy);
+      if (gmode) adj3_point<false, M_GATHER>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dsc, dummy);
+      else adj3_point<false, M_GLOBAL>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dsc, dummy);
     }
   }
   __syncthreads();  // every staged field has been read
@@ -421,6 +453,40 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
     }
   }
   __syncthreads();
+
+  if (lmode) {
+    // Interp^T of the own points into an LDS box over P +- 2 (both cotangent
+    // fields; the records' space is free in this mode), then one global
+    // atomic per touched cell into the accumulator the previous step cleared
+    float* acc = stage;
+    for (int i = threadIdx.x; i < 2 * LBOX / 4; i += NT) stage4[i] = vf4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const Scat& q = osc[k];
+      if (q.ib == 0.f && q.zhb == 0.f) continue;
+      const float wz[2] = {1.f - q.fz, q.fz}, wy[2] = {1.f - q.fy, q.fy}, wx[2] = {1.f - q.fx, q.fx};
+      const int c0 = lidx(q.cx, q.cy, q.cz);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int bz = c >> 2, by = (c >> 1) & 1, bx = c & 1;
+        const float w = wz[bz] * wy[by] * wx[bx];
+        const int o = c0 + bz * LPL + by * LXW + bx;
+        atomicAdd(acc + o, w * q.ib);
+        atomicAdd(acc + LBOX + o, w * q.zhb);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < LBOX; i += NT) {
+      const int lz = i / LPL, rem = i - LPL * (i / LPL), ly = rem / LXW, lx = rem - LXW * (rem / LXW);
+      const int x = C.x0 - 2 + lx, y = C.y0 - 2 + ly, z = C.z0 - 2 + lz;
+      if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) continue;
+      const unsigned o = (unsigned)((z * ny + y) * nx + x);
+      const float a = acc[i], b = acc[LBOX + i];
+      if (a != 0.f) unsafeAtomicAdd(C.SI + o, a);
+      if (b != 0.f) unsafeAtomicAdd(C.SZ + o, b);
+    }
+  }
 
   // phase 2: the thread's outputs are x = 4 gx + k of its row
   const int plx = 4 * gx;
