@@ -194,8 +194,6 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
           const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
           const vf4 zc = gld4(Z, idx);
           const vf4 ic = gld4(I, idx);
-          const vf4 il = gld4u(I, x > 0 ? idx - 1u : idx);
-          const vf4 ir = gld4u(I, x + 4 < nx ? idx + 1u : idx);
           const vf4 iu = gld4(I, idx + yu), id = gld4(I, idx - yd);
           vf4 izu = ic, izd = ic;
           if (NDIM == 3) {
@@ -204,8 +202,15 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
             izu = gld4(I, idx + zu);
             izd = gld4(I, idx - zd);
           }
-          const vf4 lm = x > 0 ? il : vf4{ic.x, ic.x, ic.y, ic.z};
-          const vf4 rp = x + 4 < nx ? ir : vf4{ic.y, ic.z, ic.w, ic.w};
+          // x neighbours: the adjacent lanes hold the adjacent groups of the
+          // row (items are consecutive across lanes); the wave's end lanes
+          // load theirs, the row's ends clamp
+          const int lane = threadIdx.x & 63;
+          float left = __shfl_up(ic.w, 1, 64), right = __shfl_down(ic.x, 1, 64);
+          if (lane == 0 && x > 0) left = gld(I, idx - 1u);
+          if (lane == 63 && x + 4 < nx) right = gld(I, idx + 4u);
+          const vf4 lm = x > 0 ? vf4{left, ic.x, ic.y, ic.z} : vf4{ic.x, ic.x, ic.y, ic.z};
+          const vf4 rp = x + 4 < nx ? vf4{ic.y, ic.z, ic.w, right} : vf4{ic.y, ic.z, ic.w, ic.w};
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const float zq = 0.5f * zc[k];
