@@ -405,22 +405,47 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
   Rec5 orec[4], rrec[RING_B];
   Scat osc[4], dsc;
   float vq[4][3];
+  // one loop per mode (block-uniform), so that each mode's code is contiguous
+  if (gmode) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const bool act = orow && C.x0 + gx + 4 * k < nx;
-    if (gmode) adj3_point<true, M_GATHER>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
-    else if (lmode) adj3_point<true, M_LDS>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
-    else adj3_point<true, M_GLOBAL>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    for (int k = 0; k < 4; ++k) {
+      const bool act = orow && C.x0 + gx + 4 * k < nx;
+      adj3_point<true, M_GATHER>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    }
+  } else if (lmode) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool act = orow && C.x0 + gx + 4 * k < nx;
+      adj3_point<true, M_LDS>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool act = orow && C.x0 + gx + 4 * k < nx;
+      adj3_point<true, M_GLOBAL>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    }
   }
+  if (gmode) {
 #pragma unroll
-  for (int u = 0; u < RING_B; ++u) {
-    if ((int)threadIdx.x + u * NT < NRING) {
-      const int lx = (int)(rc[u] & 255u) - 1, ly = (int)((rc[u] >> 8) & 255u) - 1, lz = (int)(rc[u] >> 16) - 1;
-      const int qx = C.x0 + lx, qy = C.y0 + ly, qz = C.z0 + lz;
-      const bool act = qx >= 0 && qx < nx && qy >= 0 && qy < ny && qz >= 0 && qz < nz;
-      float dummy[3];
-      if (gmode) adj3_point<false, M_GATHER>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dsc, dummy);
-      else adj3_point<false, M_GLOBAL>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dsc, dummy);
+    for (int u = 0; u < RING_B; ++u) {
+      if ((int)threadIdx.x + u * NT < NRING) {
+        const int lx = (int)(rc[u] & 255u) - 1, ly = (int)((rc[u] >> 8) & 255u) - 1, lz = (int)(rc[u] >> 16) - 1;
+        const int qx = C.x0 + lx, qy = C.y0 + ly, qz = C.z0 + lz;
+        const bool act = qx >= 0 && qx < nx && qy >= 0 && qy < ny && qz >= 0 && qz < nz;
+        float dummy[3];
+        adj3_point<false, M_GATHER>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dsc, dummy);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < RING_B; ++u) {
+      if ((int)threadIdx.x + u * NT < NRING) {
+        const int lx = (int)(rc[u] & 255u) - 1, ly = (int)((rc[u] >> 8) & 255u) - 1, lz = (int)(rc[u] >> 16) - 1;
+        const int qx = C.x0 + lx, qy = C.y0 + ly, qz = C.z0 + lz;
+        const bool act = qx >= 0 && qx < nx && qy >= 0 && qy < ny && qz >= 0 && qz < nz;
+        float dummy[3];
+        adj3_point<false, M_GLOBAL>(C, lx, ly, lz, act, rib[u], rzb[u], rrec[u], dsc, dummy);
+      }
     }
   }
   __syncthreads();  // every staged field has been read
