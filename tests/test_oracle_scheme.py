@@ -118,8 +118,10 @@ def test_regulariser_is_v0_norm_plus_rho_l2():
 
 
 def test_energy_drift_is_small_for_small_steps():
-    """Diagnostic only (parity unpinned): the discrete energy
-    ||v_t||_V^2 + rho ||z_t||^2 should change little along the shooting."""
+    """The discrete energy ||v_t||_V^2 + rho ||z_t||^2 (pinned itself by
+    closed forms in test_oracle_descent.py) changes little along the
+    shooting: the continuous geodesic conserves it, the discrete scheme only
+    approximately, so this is a loose sanity bound, not a parity pin."""
     pair = G.small_pair((32, 32), 4, rho=0.5, sigma=2.0)
     T = 10
     tr = O.shoot(pair.source, pair.p0, pair.rho, pair.sigma, T)
