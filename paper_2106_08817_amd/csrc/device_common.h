@@ -93,9 +93,10 @@ struct Axis {
 __device__ __forceinline__ Axis foot_axis(int q, float d, int n) {
   const float qf = (float)q;
   const float lo = -qf, hi = (float)(n - 1) - qf;
-  // clamp with one median-of-three; a NaN d gives lo
+  // clamp with one median-of-three; a NaN d gives 0 (the foot at the arrival
+  // point), so that a foot never leaves the neighbourhood a kernel stages
   const float m = __builtin_amdgcn_fmed3f(d, lo, hi);
-  const float e = m == m ? m : lo;
+  const float e = m == m ? m : 0.f;
   const float kf = floorf(e);
   const int yb = q + (int)kf;
   const bool top = yb > n - 2;              // only when the foot is on the last line

@@ -129,7 +129,7 @@ __device__ __forceinline__ float tap2(float e) {
 }
 
 // One axis of a foot (the forward step's local form): clamped offset
-// e = clamp(d, -q, n - 1 - q) (a NaN d gives -q), cell i = min(q + floor(e),
+// e = clamp(d, -q, n - 1 - q) (a NaN d gives 0), cell i = min(q + floor(e),
 // n - 2), fraction f = e - floor(e) (1 on the last grid line), live = 1 where
 // the coordinate is not clamped.
 struct Foot {
@@ -140,7 +140,7 @@ __device__ __forceinline__ Foot foot3(int q, float d, int n) {
   const float qf = (float)q;
   const float lo = -qf, hi = (float)(n - 1) - qf;
   const float m = __builtin_amdgcn_fmed3f(d, lo, hi);
-  const float e = m == m ? m : lo;
+  const float e = m == m ? m : 0.f;
   const float kf = floorf(e);
   const int yb = q + (int)kf;
   const bool top = yb > n - 2;

@@ -56,3 +56,29 @@ def test_non_finite_input_fails_before_any_output(field, bad, at):
     torch.cuda.synchronize()
     assert np.all(host(plan.out_cost) == -7.0)
     assert all(np.all(host(g) == -7.0) for g in plan.out_grad)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_nan_momentum_without_the_check_propagates(ndim):
+    """Without SHOOT_CHECK_FINITE a NaN in one pair's p0 makes that pair's
+    cost and gradient NaN; the other pairs of the launch keep the values of a
+    plan without the bad pair (a NaN displacement puts the foot at its
+    arrival point, inside every staged neighbourhood)."""
+    if ndim == 2:
+        pairs, T = batch()
+    else:
+        pairs = [G.small_pair(s, seed=960 + i, rho=0.3, sigma=1.5, p0_kind="realistic", lam=0.01)
+                 for i, s in enumerate([(12, 18, 40), (10, 14, 21)])]
+        T = 4
+    sp = specs(pairs)
+    clean = Plan(specs(pairs), T)
+    clean.grad()
+    sp[0].p0.view(-1)[sp[0].p0.numel() // 2] = float("nan")
+    plan = Plan(sp, T)
+    plan.grad()
+    torch.cuda.synchronize()
+    assert np.isnan(host(plan.out_cost[0])[0])
+    assert np.isnan(host(plan.out_grad[0])).any()
+    for i in range(1, len(pairs)):
+        assert np.array_equal(host(plan.out_cost[i]), host(clean.out_cost[i]))
+        assert np.array_equal(host(plan.out_grad[i]), host(clean.out_grad[i]))
