@@ -96,10 +96,15 @@ def family_of(kernel_name: str) -> str:
 
 
 def kernel_source_sha() -> str:
+    """Hash of every device source and header of the library (the kernels'
+    code), in name order."""
     h = hashlib.sha256()
-    for name in ("kernels.hip", "device_common.h", "shoot_internal.h"):
-        with open(os.path.join(ROOT, "paper_2106_08817_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2106_08817_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
