@@ -100,3 +100,37 @@ def test_scratch_descent_resets_after_another_plan_ran():
     torch.cuda.synchronize()
     assert np.array_equal(host(sa.pairs[0].p0), host(ra.pairs[0].p0))
     assert np.array_equal(host(sa.out_cost), host(ra.out_cost))
+
+
+def test_scratch_plan_keeps_its_pair_selection_across_other_plans():
+    """A pair selection on a scratch plan survives another scratch plan's
+    call (whose header overwrote the array): the re-uploaded descriptors
+    still skip the inactive pair, whose outputs stay as they were."""
+    pairs = [G.small_pair(s, 80 + i, rho=0.5, sigma=1.8) for i, s in enumerate([(40, 52), (33, 29), (48, 36)])]
+    other = [G.small_pair((30, 34), 90, rho=0.3, sigma=1.5)]
+    T = 5
+    sp = specs(pairs)
+    a = Plan(sp, T, FL, scratch=True)
+    a.grad()
+    torch.cuda.synchronize()
+    old_g, old_c = host(a.out_grad[1]).copy(), host(a.out_cost[1]).copy()
+    for s in sp:
+        s.p0.mul_(0.5)
+    a.set_active([True, False, True])
+    b = Plan(specs(other), T, FL, scratch=True)
+    b.grad()                      # the array now holds b's header
+    a.grad()                      # a's header, selection included, goes up again
+    torch.cuda.synchronize()
+    ref = Plan(specs(pairs), T, FL)
+    for i, s in enumerate(sp):
+        ref.pairs[i].p0.copy_(s.p0)
+    ref.grad()
+    torch.cuda.synchronize()
+    for i in (0, 2):
+        assert np.array_equal(host(a.out_grad[i]), host(ref.out_grad[i]))
+    assert np.array_equal(host(a.out_grad[1]), old_g)
+    assert np.array_equal(host(a.out_cost[1]), old_c)
+    a.set_active(None)            # owner now: uploaded at once
+    a.grad()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(a.out_grad[1]), host(ref.out_grad[1]))
