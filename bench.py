@@ -697,7 +697,7 @@ def main():
             ls = synthetic.large_step(wl)
             r = measure(ls, "c5 large-step", args.steps, args.warmup, 1, args.flags, autotune, torch, api)
             r["workload"] = (f"c5 images, realistic momentum x {synthetic.LARGE_STEP_SCALE:g}, rho = 0, T = {ls.T}: "
-                             "feet move ~1-2 voxels per step")
+                             "feet move ~1-2.5 voxels per step")
             extra["batched_3d_c5_large_step"] = strip(r)
         # the single 2-D pair: throughput, then its gradient descent and the
         # throughput at the momentum the descent reached

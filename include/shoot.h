@@ -392,7 +392,8 @@ shoot_status shoot_stream_copy(const void* src, void* dst, size_t bytes, void* s
  * the last execution call (its forward pass): out[i * T + t] for pair i and
  * step t, host memory of n_pairs * T floats. The adjoint of a step takes the
  * LDS gather when this is below 2 px (2-D) or 1 voxel (3-D), in 3-D the
- * scatter into an LDS box below 2 voxels, else the global atomic scatter. Synchronises `stream` (SHOOT_E_STATE under capture);
+ * scatter into an LDS box below 3 voxels, else the global atomic scatter.
+ * Synchronises `stream` (SHOOT_E_STATE under capture);
  * SHOOT_E_ARG for SHOOT_UNFUSED plans. Values before the first execution call
  * are unspecified.
  */

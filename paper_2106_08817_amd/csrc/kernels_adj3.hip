@@ -30,13 +30,15 @@
 // reaches, in a fixed order, without atomics: deterministic, each output
 // written once.
 //
-// When 1 <= D < 2 voxels every corner of an own point's foot lies in P +- 2:
-// the block adds its own points' Interp^T with LDS atomics into a box over
-// P +- 2 (in the records' space) and then adds each touched cell of the box
-// with one global float atomic into the accumulator that the previous adjoint
-// step (or the last forward step) cleared, about a third of the global
-// atomics of a per-corner scatter. When D >= 2 (or a forced global scatter)
-// the own points scatter per corner with global float atomics. In both the
+// When 1 <= D < 3 voxels every corner of an own point's foot lies in P +- M,
+// M = 2 below two voxels and 3 above: the block adds its own points'
+// Interp^T with LDS atomics into a box over P +- M (in the records' space)
+// and then adds each touched cell of the box with one global float atomic
+// into the accumulator that the previous adjoint step (or the last forward
+// step) cleared, a fraction of the global atomics of a per-corner scatter.
+// Below two voxels the own points' foot corners come from the staged fields,
+// above from global memory. When D >= 3 (or a forced global scatter) the own
+// points scatter per corner with global float atomics. In all these modes the
 // ring points' foot corners come from global memory; velocity and divergence
 // still come from LDS. Sums through atomics depend on their order.
 #include "kernels.h"
@@ -82,9 +84,14 @@ constexpr int RX = AX + 2, RY = AY + 2, RZ = AZ + 2;
 constexpr int RXP = AX + 3;
 constexpr int NRP = RXP * RY * RZ;
 constexpr int NOWN = AX * AY * AZ;
-// LDS scatter box over P +- 2 (1 <= D < 2): rows of LXW floats
-constexpr int LXW = AX + 4, LPL = LXW * (AY + 4), LBOX = LPL * (AZ + 4);
-__device__ __forceinline__ int lidx(int cx, int cy, int cz) { return ((cz + 2) * (AY + 4) + cy + 2) * LXW + cx + 2; }
+// LDS scatter box over P +- M (M = 2 for 1 <= D < 2, 3 for 2 <= D < 3):
+// rows of XW floats, N floats per cotangent field
+template <int M>
+struct LBox {
+  static constexpr int XW = AX + 2 * M, PL = XW * (AY + 2 * M), N = PL * (AZ + 2 * M);
+  // box index of the cell (cx, cy, cz) relative to the tile origin
+  __device__ static int idx(int cx, int cy, int cz) { return ((cz + M) * (AY + 2 * M) + cy + M) * XW + cx + M; }
+};
 constexpr int NRING = RX * RY * RZ - NOWN;
 constexpr int RING_B = (NRING + NT - 1) / NT;  // ring points per thread (rounds)
 // the own points' foot-point parts of vbar, handed from phase 1 to phase 2
@@ -95,7 +102,9 @@ static_assert(SXW % 4 == 0 && SPL % 4 == 0 && BOXP % 4 == 0, "16-byte groups");
 static_assert(O_VQ % 4 == 0 && VQR % 4 == 0 && VQP % 4 == 0, "16-byte vbar rows");
 static_assert(O_VQ + 3 * VQN <= NF * BOXP, "records and vbar parts fit in the staged fields' space");
 static_assert(FILL_U % 2 == 0, "fill rounds in pairs");
-static_assert(2 * LBOX % 4 == 0 && 2 * LBOX <= O_VQ, "the LDS scatter box fits below the vbar parts");
+static_assert(2 * LBox<2>::N % 4 == 0 && 2 * LBox<3>::N % 4 == 0 && 2 * LBox<2>::N <= O_VQ &&
+                  2 * LBox<3>::N <= O_VQ,
+              "the LDS scatter boxes fit below the vbar parts");
 
 constexpr int SBY = SXW, SBZ = SPL;
 __device__ __forceinline__ int bidx(int lx, int ly, int lz) { return (lz + 2) * SPL + (ly + 2) * SXW + lx + 4; }
@@ -198,9 +207,10 @@ struct Adj3Ctx {
 
 // How a block forms Interp^T (chosen per pair and step from D = max |dt v|):
 // a gather over the records in LDS (D < 1), atomics into an LDS box over
-// P +- 2 flushed with one global atomic per cell (1 <= D < 2), or global
-// atomics per corner (D >= 2, or a forced global scatter).
-constexpr int M_GATHER = 0, M_LDS = 1, M_GLOBAL = 2;
+// P +- 2 (1 <= D < 2) or P +- 3 (2 <= D < 3) flushed with one global atomic
+// per cell, or global atomics per corner (D >= 3, or a forced global
+// scatter).
+constexpr int M_GATHER = 0, M_LDS2 = 1, M_LDS3 = 2, M_GLOBAL = 3;
 
 // A foot's cell (relative to the tile origin), fractions and cotangents, for
 // the LDS scatter.
@@ -212,14 +222,14 @@ struct Scat {
 // Phase 1 at one arrival point, local coordinates (lx, ly, lz) in P +- 1.
 // The point's computations use its coordinates clamped into the image; act
 // marks a point inside the image (only those contribute). The foot corners
-// come from LDS in M_GATHER, and for own points in M_LDS (|e| < 2 keeps them
+// come from LDS in M_GATHER, and for own points in M_LDS2 (|e| < 2 keeps them
 // within P +- 2); otherwise from global memory. M_GATHER keeps the record,
-// M_LDS the foot's cell and weights, M_GLOBAL scatters an own point's
-// Interp^T with global atomics.
+// M_LDS2 and M_LDS3 the foot's cell and weights, M_GLOBAL scatters an own
+// point's Interp^T with global atomics.
 template <bool OWN, int MODE>
 __device__ __forceinline__ void adj3_point(const Adj3Ctx& C, int lx, int ly, int lz, bool act, float ib, float zb,
                                            Rec5& rec, Scat& sc, float vq[3]) {
-  constexpr bool STAGED = MODE == M_GATHER || (MODE == M_LDS && OWN);
+  constexpr bool STAGED = MODE == M_GATHER || (MODE == M_LDS2 && OWN);
   const int qx = clampi3(C.x0 + lx, C.nx), qy = clampi3(C.y0 + ly, C.ny), qz = clampi3(C.z0 + lz, C.nz);
   const int b = bidx(qx - C.x0, qy - C.y0, qz - C.z0);
   const float* S = C.st;
@@ -270,7 +280,7 @@ __device__ __forceinline__ void adj3_point(const Adj3Ctx& C, int lx, int ly, int
     rec.ez = act ? az.e : 0.f;
     rec.ib = act ? 0.125f * ib : 0.f;
     rec.zhb = act ? 0.125f * zhb : 0.f;
-  } else if (MODE == M_LDS && OWN) {
+  } else if ((MODE == M_LDS2 || MODE == M_LDS3) && OWN) {
     sc.cx = ax.i - C.x0; sc.cy = ay.i - C.y0; sc.cz = az.i - C.z0;
     sc.fx = ax.f; sc.fy = ay.f; sc.fz = az.f;
     sc.ib = act ? ib : 0.f;
@@ -287,6 +297,43 @@ __device__ __forceinline__ void adj3_point(const Adj3Ctx& C, int lx, int ly, int
       unsafeAtomicAdd(C.SI + o, w * ib);
       unsafeAtomicAdd(C.SZ + o, w * zhb);
     }
+  }
+}
+
+// Interp^T of the own points (cells and weights in osc) into an LDS box over
+// P +- M, both cotangent fields side by side in the records' space, then one
+// global atomic per touched cell of the box into the accumulator the previous
+// step cleared. Called by the whole block.
+template <int M>
+__device__ __forceinline__ void lds_scatter(const Adj3Ctx& C, vf4* stage4, const Scat osc[4]) {
+  using Bx = LBox<M>;
+  float* acc = reinterpret_cast<float*>(stage4);
+  for (int i = threadIdx.x; i < 2 * Bx::N / 4; i += NT) stage4[i] = vf4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const Scat& q = osc[k];
+    if (q.ib == 0.f && q.zhb == 0.f) continue;
+    const float wz[2] = {1.f - q.fz, q.fz}, wy[2] = {1.f - q.fy, q.fy}, wx[2] = {1.f - q.fx, q.fx};
+    const int c0 = Bx::idx(q.cx, q.cy, q.cz);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int bz = c >> 2, by = (c >> 1) & 1, bx = c & 1;
+      const float w = wz[bz] * wy[by] * wx[bx];
+      const int o = c0 + bz * Bx::PL + by * Bx::XW + bx;
+      atomicAdd(acc + o, w * q.ib);
+      atomicAdd(acc + Bx::N + o, w * q.zhb);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < Bx::N; i += NT) {
+    const int lz = i / Bx::PL, rem = i - Bx::PL * (i / Bx::PL), ly = rem / Bx::XW, lx = rem - Bx::XW * (rem / Bx::XW);
+    const int x = C.x0 - M + lx, y = C.y0 - M + ly, z = C.z0 - M + lz;
+    if (x < 0 || x >= C.nx || y < 0 || y >= C.ny || z < 0 || z >= C.nz) continue;
+    const unsigned o = (unsigned)((z * C.ny + y) * C.nx + x);
+    const float a = acc[i], b = acc[Bx::N + i];
+    if (a != 0.f) unsafeAtomicAdd(C.SI + o, a);
+    if (b != 0.f) unsafeAtomicAdd(C.SZ + o, b);
   }
 }
 
@@ -320,7 +367,8 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
   const unsigned N = C.N;
   const float D = __uint_as_float(A.dmax[(long long)tl.pair * A.T + A.t]);
   const bool gmode = !A.force_global && D < 1.f;
-  const bool lmode = !A.force_global && !gmode && D < 2.f;
+  const bool lmode2 = !A.force_global && !gmode && D < 2.f;
+  const bool lmode3 = !A.force_global && !gmode && !lmode2 && D < 3.f;
   const bool vec = (nx & 3) == 0;
 
   const int gx = threadIdx.x & 3, oly = (threadIdx.x >> 2) & (AY - 1), olz = threadIdx.x >> 5;
@@ -412,11 +460,17 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
       const bool act = orow && C.x0 + gx + 4 * k < nx;
       adj3_point<true, M_GATHER>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
     }
-  } else if (lmode) {
+  } else if (lmode2) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const bool act = orow && C.x0 + gx + 4 * k < nx;
-      adj3_point<true, M_LDS>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+      adj3_point<true, M_LDS2>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
+    }
+  } else if (lmode3) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool act = orow && C.x0 + gx + 4 * k < nx;
+      adj3_point<true, M_LDS3>(C, gx + 4 * k, oly, olz, act, ib[k], zb[k], orec[k], osc[k], vq[k]);
     }
   } else {
 #pragma unroll
@@ -479,39 +533,8 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
   }
   __syncthreads();
 
-  if (lmode) {
-    // Interp^T of the own points into an LDS box over P +- 2 (both cotangent
-    // fields; the records' space is free in this mode), then one global
-    // atomic per touched cell into the accumulator the previous step cleared
-    float* acc = stage;
-    for (int i = threadIdx.x; i < 2 * LBOX / 4; i += NT) stage4[i] = vf4{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const Scat& q = osc[k];
-      if (q.ib == 0.f && q.zhb == 0.f) continue;
-      const float wz[2] = {1.f - q.fz, q.fz}, wy[2] = {1.f - q.fy, q.fy}, wx[2] = {1.f - q.fx, q.fx};
-      const int c0 = lidx(q.cx, q.cy, q.cz);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int bz = c >> 2, by = (c >> 1) & 1, bx = c & 1;
-        const float w = wz[bz] * wy[by] * wx[bx];
-        const int o = c0 + bz * LPL + by * LXW + bx;
-        atomicAdd(acc + o, w * q.ib);
-        atomicAdd(acc + LBOX + o, w * q.zhb);
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < LBOX; i += NT) {
-      const int lz = i / LPL, rem = i - LPL * (i / LPL), ly = rem / LXW, lx = rem - LXW * (rem / LXW);
-      const int x = C.x0 - 2 + lx, y = C.y0 - 2 + ly, z = C.z0 - 2 + lz;
-      if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) continue;
-      const unsigned o = (unsigned)((z * ny + y) * nx + x);
-      const float a = acc[i], b = acc[LBOX + i];
-      if (a != 0.f) unsafeAtomicAdd(C.SI + o, a);
-      if (b != 0.f) unsafeAtomicAdd(C.SZ + o, b);
-    }
-  }
+  if (lmode2) lds_scatter<2>(C, stage4, osc);
+  else if (lmode3) lds_scatter<3>(C, stage4, osc);
 
   // phase 2: the thread's outputs are x = 4 gx + k of its row
   const int plx = 4 * gx;
