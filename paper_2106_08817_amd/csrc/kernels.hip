@@ -50,6 +50,8 @@ struct Blk {
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+// quotient of two non-negative ints as unsigned division (no sign handling)
+__device__ __forceinline__ unsigned udiv(int a, int b) { return (unsigned)a / (unsigned)b; }
 
 // ----------------------------------------------------------------------------
 // small utility kernels
@@ -151,7 +153,8 @@ __global__ __launch_bounds__(NT) void k_count_nonfinite(const PairDev* __restric
 // the row shifted one element either way); otherwise it loads one element per
 // lane. A thread produces four consecutive outputs of one row; the taps run in
 // blocks of four (weights zero past 2r), so each block reads one new aligned
-// float4 of the row and does 16 FMAs.
+// float4 of the row and does 16 FMAs, and the last block applies only its
+// nonzero taps.
 template <int NDIM, bool GRADMUL>
 __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, const Tile* __restrict__ tl,
                                               const float* __restrict__ src, float* __restrict__ dst) {
@@ -181,23 +184,31 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
     for (int i0 = threadIdx.x; i0 < ni; i0 += XV * NT) {
       vf4 m[XV][NDIM];
       int lcol[XV];
+      // the wave's first item: a wave whose items all lie past the tile skips
+      // the batch slot (the whole wave, so that the lane shuffles below always
+      // run on full waves)
+      const int wfirst = __builtin_amdgcn_readfirstlane(i0 - (int)(threadIdx.x & 63));
 #pragma unroll
       for (int u = 0; u < XV; ++u) {
+        if (wfirst + u * NT >= ni) {
+          lcol[u] = -1;
+          continue;
+        }
         const int i = min(i0 + u * NT, ni - 1);
-        const int rl = i / G;
+        const int rl = (int)udiv(i, G);
         const int x = 4 * (i - rl * G);
         lcol[u] = i0 + u * NT < ni ? rl * L + r + x : -1;
         const int row = row0 + rl;
         const unsigned idx = (unsigned)(row * nx + x);
         if (GRADMUL) {
-          const int y = row % ny;
+          const int y = row - ny * (int)udiv(row, ny);
           const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
           const vf4 zc = gld4(Z, idx);
           const vf4 ic = gld4(I, idx);
           const vf4 iu = gld4(I, idx + yu), id = gld4(I, idx - yd);
           vf4 izu = ic, izd = ic;
           if (NDIM == 3) {
-            const int z = row / ny;
+            const int z = (int)udiv(row, ny);
             const unsigned zu = (unsigned)up(z, nz, ny * nx), zd = (unsigned)dn(z, ny * nx);
             izu = gld4(I, idx + zu);
             izd = gld4(I, idx - zd);
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
     // zero padding: r columns in front of each row, the rest of the row behind
     const int pad = L - nx;
     for (int i = threadIdx.x; i < nrows * pad; i += NT) {
-      const int rl = i / pad;
+      const int rl = (int)udiv(i, pad);
       const int k = i - rl * pad;
       const int col = k < r ? k : nx + k;
 #pragma unroll
@@ -260,7 +271,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
 #pragma unroll
     for (int u = 0; u < XSEG; ++u) {
       const int sg = min(sb + wv + u * (NT / 64), nseg - 1);  // wave-uniform
-      const int rl = sg / nch;
+      const int rl = (int)udiv(sg, nch);
       const int col = (sg - rl * nch) * 64 + lane;
       lcol[u] = (sb + wv + u * (NT / 64) < nseg && col < L) ? rl * L + col : -1;
       const int row = row0 + rl;
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
       const unsigned idx = (unsigned)(row * nx + xc);
       const bool in = x >= 0 && x < nx;
       if (GRADMUL) {
-        const int y = row % ny;
+        const int y = row - ny * (int)udiv(row, ny);
         const unsigned yu = (unsigned)up(y, ny, nx), yd = (unsigned)dn(y, nx);
         const float zq = 0.5f * gld(Z, idx);
         const float gx = gld(I, idx + (xc + 1 < nx ? 1u : 0u)) - gld(I, idx - (xc > 0 ? 1u : 0u));
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
         m[u][NDIM - 1] = in ? zq * gx : 0.f;
         m[u][NDIM - 2] = in ? zq * gy : 0.f;
         if (NDIM == 3) {
-          const int z = row / ny;
+          const int z = (int)udiv(row, ny);
           const unsigned zu = (unsigned)up(z, nz, ny * nx), zd = (unsigned)dn(z, ny * nx);
           m[u][0] = in ? zq * (gld(I, idx + zu) - gld(I, idx - zd)) : 0.f;
         }
@@ -301,10 +312,13 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
   __syncthreads();
 
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
+  // 2r + 1 taps: nfull blocks of four, then rem taps (the rest of the padded
+  // last block has zero weights, which leave a finite sum unchanged)
+  const int nfull = (2 * r + 1) >> 2, rem = (2 * r + 1) & 3;
   float* __restrict__ D = dst + NDIM * P.off;
   const int ngroups = nrows * G4;
   for (int g = threadIdx.x; g < ngroups; g += NT) {
-    const int rl = g / G4;
+    const int rl = (int)udiv(g, G4);
     const int x = 4 * (g - rl * G4);
     const unsigned obase = (unsigned)((row0 + rl) * nx + x);
 #pragma unroll
@@ -314,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
       const vf4* R4 = smem4 + ((c * plane + rl * L + x) >> 2);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
       vf4 lo = R4[0];
-      for (int b = 0; b < ntap4; ++b) {
+      for (int b = 0; b < nfull; ++b) {
         const vf4 hi = R4[b + 1];
         const float4 w = W4[b];
         a0 = fmaf(w.x, lo.x, a0); a1 = fmaf(w.x, lo.y, a1); a2 = fmaf(w.x, lo.z, a2); a3 = fmaf(w.x, lo.w, a3);
@@ -322,6 +336,17 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
         a0 = fmaf(w.z, lo.z, a0); a1 = fmaf(w.z, lo.w, a1); a2 = fmaf(w.z, hi.x, a2); a3 = fmaf(w.z, hi.y, a3);
         a0 = fmaf(w.w, lo.w, a0); a1 = fmaf(w.w, hi.x, a1); a2 = fmaf(w.w, hi.y, a2); a3 = fmaf(w.w, hi.z, a3);
         lo = hi;
+      }
+      if (rem > 0) {  // the last block's nonzero taps, in the same order
+        const float4 w = W4[nfull];
+        a0 = fmaf(w.x, lo.x, a0); a1 = fmaf(w.x, lo.y, a1); a2 = fmaf(w.x, lo.z, a2); a3 = fmaf(w.x, lo.w, a3);
+        if (rem > 1) {
+          const vf4 hi = R4[nfull + 1];
+          a0 = fmaf(w.y, lo.y, a0); a1 = fmaf(w.y, lo.z, a1); a2 = fmaf(w.y, lo.w, a2); a3 = fmaf(w.y, hi.x, a3);
+          if (rem > 2) {
+            a0 = fmaf(w.z, lo.z, a0); a1 = fmaf(w.z, lo.w, a1); a2 = fmaf(w.z, hi.x, a2); a3 = fmaf(w.z, hi.y, a3);
+          }
+        }
       }
       float* o = D + c * N + obase;
       if ((nx & 3) == 0) {
@@ -347,7 +372,7 @@ __global__ __launch_bounds__(NT) void k_xpass(const PairDev* __restrict__ pd, co
 // one dwordx4 access) x 16 row groups; a thread produces RB / 4 consecutive
 // outputs along the axis for its four columns, reading the LDS window as
 // aligned 16-byte vectors. Every output sums its taps in blocks of four in the
-// same order whatever RB is.
+// same order whatever RB is (the last block's nonzero taps only).
 // MODE 0: plain pass. MODE 1: negated (v = -G m). MODE 2: negated, plus
 // -2 lambda * extra (the regulariser's cotangent at t = 0).
 template <int NDIM, bool PASSZ, int MODE, int RB>
@@ -417,7 +442,10 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
   for (int i = 0; i < RQ; ++i) acc[i] = vf4{0.f, 0.f, 0.f, 0.f};
   const float4* W4 = reinterpret_cast<const float4*>(P.w);
   const vf4* col = smem4 + (rg * RQ) * 16 + cg;
-  for (int b = 0; b < ntap4; ++b) {
+  // 2r + 1 taps: nfull blocks of four, then rem taps (the rest of the padded
+  // last block has zero weights, which leave a finite sum unchanged)
+  const int nfull = (2 * r + 1) >> 2, rem = (2 * r + 1) & 3;
+  for (int b = 0; b < nfull; ++b) {
     const float4 w = W4[b];
     vf4 win[RQ + 3];
 #pragma unroll
@@ -431,6 +459,23 @@ __global__ __launch_bounds__(NT) void k_spass(const PairDev* __restrict__ pd, co
         a = fmaf(w.y, win[i + 1][k], a);
         a = fmaf(w.z, win[i + 2][k], a);
         a = fmaf(w.w, win[i + 3][k], a);
+        acc[i][k] = a;
+      }
+    }
+  }
+  if (rem > 0) {
+    const float4 w = W4[nfull];
+    vf4 win[RQ + 2];
+#pragma unroll
+    for (int j = 0; j < RQ + 2; ++j) win[j] = col[(4 * nfull + j) * 16];
+#pragma unroll
+    for (int i = 0; i < RQ; ++i) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float a = acc[i][k];
+        a = fmaf(w.x, win[i][k], a);
+        if (rem > 1) a = fmaf(w.y, win[i + 1][k], a);
+        if (rem > 2) a = fmaf(w.z, win[i + 2][k], a);
         acc[i][k] = a;
       }
     }
@@ -710,9 +755,16 @@ __device__ __forceinline__ void stage_tile(int x0, int y0, int z0, int nx, int n
     const int gz = NDIM == 3 ? clampi(z0 + oz + bz, 0, nz - 1) : 0;
     return (unsigned)((gz * ny + gy) * nx + gx);
   };
+  // a wave whose slots of a round all lie past the box skips that round (the
+  // stores below skip those slots)
+  const int wfirst = __builtin_amdgcn_readfirstlane((int)threadIdx.x);  // the wave's first thread
   float a[UI], b[UI], cx[UX], cy[UY], cz[UZ > 0 ? UZ : 1];
 #pragma unroll
   for (int u = 0; u < UI; ++u) {
+    if (wfirst + u * NT >= S::NS) {
+      a[u] = b[u] = 0.f;
+      continue;
+    }
     const int j = min((int)threadIdx.x + u * NT, S::NS - 1);
     const unsigned g = gidx(j % SX, (j / SX) % SY, j / (SX * SY), -1, -1, -1);
     a[u] = gld(F0, g);
@@ -720,16 +772,28 @@ __device__ __forceinline__ void stage_tile(int x0, int y0, int z0, int nx, int n
   }
 #pragma unroll
   for (int u = 0; u < UX; ++u) {
+    if (wfirst + u * NT >= S::NVX) {
+      cx[u] = 0.f;
+      continue;
+    }
     const int j = min((int)threadIdx.x + u * NT, S::NVX - 1);
     cx[u] = gld(Cx, gidx(j % SX, (j / SX) % Y, j / (SX * Y), -1, 0, 0));
   }
 #pragma unroll
   for (int u = 0; u < UY; ++u) {
+    if (wfirst + u * NT >= S::NVY) {
+      cy[u] = 0.f;
+      continue;
+    }
     const int j = min((int)threadIdx.x + u * NT, S::NVY - 1);
     cy[u] = gld(Cy, gidx(j % X, (j / X) % SY, j / (X * SY), 0, -1, 0));
   }
 #pragma unroll
   for (int u = 0; u < UZ; ++u) {
+    if (wfirst + u * NT >= S::NVZ) {
+      cz[u] = 0.f;
+      continue;
+    }
     const int j = min((int)threadIdx.x + u * NT, S::NVZ - 1);
     cz[u] = gld(Cz, gidx(j % X, (j / X) % Y, j / (X * Y), 0, 0, -1));
   }

@@ -384,11 +384,18 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
     ib[k] = gld(AB, o);
     zb[k] = gld(AB, N + o);
   }
-  // the ring points' cotangents
+  // the ring points' cotangents (a wave whose slots of a round all lie past
+  // the ring skips that round; those slots are never used)
   float rib[RING_B], rzb[RING_B];
   unsigned rc[RING_B];
+  const int wfirst = __builtin_amdgcn_readfirstlane((int)threadIdx.x);  // the wave's first thread
 #pragma unroll
   for (int u = 0; u < RING_B; ++u) {
+    if (wfirst + u * NT >= NRING) {
+      rc[u] = 0u;
+      rib[u] = rzb[u] = 0.f;
+      continue;
+    }
     rc[u] = kRing.c[min((int)threadIdx.x + u * NT, NRING - 1)];
     const int lx = (int)(rc[u] & 255u) - 1, ly = (int)((rc[u] >> 8) & 255u) - 1, lz = (int)(rc[u] >> 16) - 1;
     const unsigned o =
@@ -400,11 +407,13 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
   // staging: a fill thread takes one 16-byte group g of a staged row and the
   // same group of rows FILL_R apart; the row's global offset serves all five
   // fields (rows clamped into the image; groups left or right of the image
-  // hold the row's first or last value)
+  // hold the row's first or last value); a wave whose rows of a round all lie
+  // past the box skips that round
   {
     const float* F[NF] = {C.I, C.Z, V, V + N, V + 2 * N};
     const int t = threadIdx.x;
     const int row0 = t / G4, g = t - G4 * (t / G4);
+    const int wrow0 = __builtin_amdgcn_readfirstlane(row0);  // the wave's first row
     const int xs = C.x0 - 4 + 4 * g;
     const bool xedge = C.x0 < 4 || C.x0 + AX + 4 > nx;  // block-uniform
 #pragma unroll
@@ -414,6 +423,12 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
 #pragma unroll
       for (int mm = 0; mm < 2; ++mm) {
         const int row = row0 + FILL_R * (m0 + mm);
+        if (wrow0 + FILL_R * (m0 + mm) >= SROWS) {  // every row of the wave is past the box
+          ld[mm] = -1;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) v[mm][f] = vf4{0.f, 0.f, 0.f, 0.f};
+          continue;
+        }
         const int rr = min(row, SROWS - 1);
         const int rz = rr / SYW, ry = rr - SYW * (rr / SYW);
         ld[mm] = (t < FILL_T && row < SROWS) ? rz * SPL + ry * SXW + 4 * g : -1;

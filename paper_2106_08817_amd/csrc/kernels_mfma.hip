@@ -63,8 +63,14 @@ __global__ __launch_bounds__(NT) void k_xpass_mfma(const PairDev* __restrict__ p
   for (int i0 = threadIdx.x; i0 < ni; i0 += 2 * NT) {
     vf4 m[2][NDIM];
     int lrow[2];
+    // a wave whose items all lie past the tile skips the batch slot
+    const int wfirst = __builtin_amdgcn_readfirstlane(i0 - (int)(threadIdx.x & 63));
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
+      if (wfirst + u * NT >= ni) {
+        lrow[u] = -1;
+        continue;
+      }
       const int i = min(i0 + u * NT, ni - 1);
       const int rl = i / G;
       const int x = 4 * (i - rl * G);
