@@ -384,18 +384,13 @@ __global__ __launch_bounds__(NT, 2) void k_adv_adj3(const PairDev* __restrict__ 
     ib[k] = gld(AB, o);
     zb[k] = gld(AB, N + o);
   }
-  // the ring points' cotangents (a wave whose slots of a round all lie past
-  // the ring skips that round; those slots are never used)
+  // the ring points' cotangents (slots past the ring load the last point's
+  // and are never used: skipping them per wave measured slower, the branch
+  // splitting the batch of loads)
   float rib[RING_B], rzb[RING_B];
   unsigned rc[RING_B];
-  const int wfirst = __builtin_amdgcn_readfirstlane((int)threadIdx.x);  // the wave's first thread
 #pragma unroll
   for (int u = 0; u < RING_B; ++u) {
-    if (wfirst + u * NT >= NRING) {
-      rc[u] = 0u;
-      rib[u] = rzb[u] = 0.f;
-      continue;
-    }
     rc[u] = kRing.c[min((int)threadIdx.x + u * NT, NRING - 1)];
     const int lx = (int)(rc[u] & 255u) - 1, ly = (int)((rc[u] >> 8) & 255u) - 1, lz = (int)(rc[u] >> 16) - 1;
     const unsigned o =
