@@ -959,8 +959,22 @@ shoot_status shoot_plan_create(const shoot_pair* pairs, int32_t n_pairs, int32_t
   p->pairs.assign(pairs, pairs + n_pairs);
   for (int i = 0; i < n_pairs; ++i)
     if (pairs[i].out_deformation) p->has_def = true;
-  p->k = std::max(1, (int)std::ceil(std::sqrt((double)T) - 1e-9));
-  while ((long long)p->k * p->k < T) ++p->k;
+  // Checkpoint interval k (the sqrt(T) schedule): the k that needs the fewest
+  // state slots, ceil(T / k) checkpoints + k - 1 inside a segment, which is
+  // k = ceil(sqrt(T)) or a neighbour of it; among those the one with the fewest
+  // recomputed steps, (ceil(T / k) - 1)(k - 1); on a tie the larger k. (T = 15:
+  // k = 3, 4 and 5 all need 7 slots, 4 recomputes 9 steps, 3 and 5 recompute 8.)
+  {
+    long long best_m = -1, best_r = 0;
+    for (int k = 1; k <= T; ++k) {
+      const long long nck = (T + k - 1) / k, m = nck + k - 1, r = (nck - 1) * (k - 1);
+      if (best_m < 0 || m < best_m || (m == best_m && r <= best_r)) {
+        best_m = m;
+        best_r = r;
+        p->k = k;
+      }
+    }
+  }
   p->nck = (T + p->k - 1) / p->k;
   if (fullstore(p)) {
     p->nst = T;

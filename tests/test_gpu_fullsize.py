@@ -62,7 +62,7 @@ def test_c3_every_pair_matches_oracle():
 
 @ORACLE_WAIT
 def test_c4_full_run_matches_oracle():
-    """160x192x160, T = 15 (four checkpoints): cost, gradient, I_T and z_T."""
+    """160x192x160, T = 15 (a checkpoint every five steps): cost, gradient, I_T and z_T."""
     w = G.workload("c4")
     p = w.pairs[0]
     plan = run([p], w.T, op="grad")
