@@ -290,8 +290,9 @@ shoot_status shoot_cost(shoot_plan plan, void* stream);
 /*
  * Shoot every pair, then run the discrete adjoint backwards through the loop
  * (states restored from sqrt(T) checkpoints by recomputation, unless
- * SHOOT_FULL_STORE) and write dH/dp0 to out_grad, and the cost to out_cost
- * when given.
+ * SHOOT_FULL_STORE: a checkpoint every k steps, k the interval that needs the
+ * fewest state slots, ceil(T / k) + k - 1, and of those recomputes the fewest
+ * steps) and write dH/dp0 to out_grad, and the cost to out_cost when given.
  */
 shoot_status shoot_grad_p0(shoot_plan plan, void* stream);
 
